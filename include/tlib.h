@@ -1,0 +1,155 @@
+/*
+ * tlib -- MI355X (gfx950) tensor-contraction library, C ABI.
+ *
+ * Operations of Bassoy, "TLib: A Flexible C++ Tensor Framework for Numerical
+ * Tensor Calculus" (arXiv 1711.10912), Sec. 5: tensor-times-vector (Eq. ttv),
+ * tensor-times-matrix (Eq. ttm), tensor-times-tensor (Eq. ttt, ttt_indices),
+ * inner product and Frobenius norm (Table 3), entrywise scaling and sums
+ * (Sec. 5.1 Eq. scaling, Eq. transform) and transposition (Table 3).
+ *
+ * Tensors.  A tensor is described by a tlib_tensor: a device pointer to its
+ * element with multi-index (0,...,0), its order p, its shape tuple n and its
+ * stride tuple w in elements (Sec. 3.1).  The element with zero-based
+ * multi-index i lives at data[ sum_r w_r i_r ] (layout function, Sec. 3.2
+ * Eq. f with zero index offsets).  Either the strides are given explicitly, or
+ * they are derived from a 1-based layout tuple pi by Sec. 3.1
+ * Eq. stride.tuple.permutation (pi = NULL means first-order, Eq.
+ * layout.tuple.first.order).  A view (Sec. 3.3) is passed as its parent's
+ * pointer plus gamma (Eq. view_gamma) with strides w_r * t_r.  Strides must
+ * be >= 0; the strides of an output must map distinct multi-indices to
+ * distinct addresses (checked conservatively: sorted by stride, each stride
+ * must be at least the previous stride times its extent).
+ *
+ * Modes (m, phi, psi, tau) are 1-based as in the paper's equations.
+ *
+ * Data types.  A, B and b share one dtype.  Contractions write C in FP64 for
+ * FP64 inputs and in FP32 for FP32, BF16 and FP16 inputs (accumulation in
+ * FP64 resp. FP32).  add / scale / transpose keep the input dtype.  inner and
+ * norm accumulate and return FP64 for every input dtype.
+ *
+ * Ownership.  The caller owns every buffer.  The library never allocates or
+ * frees caller-visible memory; the small per-stream workspace it keeps for
+ * reduction partials is its own.  Host arrays (extents, strides, layout, phi,
+ * psi, tau) are read during the call only.
+ *
+ * Synchronisation.  Arguments are validated on the host before anything is
+ * launched.  Kernels are enqueued on `stream` (a hipStream_t; NULL is the
+ * default stream) and the call returns without waiting for them.  C is
+ * overwritten, never accumulated into.  Calls on one stream run in order;
+ * calls on different streams may overlap.
+ *
+ * Errors.  Every entry point returns 0 (TLIB_OK) or one of the codes below;
+ * nothing is thrown across the ABI.  On an error nothing has been launched
+ * and C is untouched (TLIB_EHIP: a launch failed; C is unspecified).
+ * tlib_last_error() returns a message for the calling thread's last error.
+ */
+#ifndef TLIB_H
+#define TLIB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TLIB_MAX_ORDER 16
+
+typedef enum { TLIB_F64 = 0, TLIB_F32 = 1, TLIB_BF16 = 2, TLIB_F16 = 3 } tlib_dtype;
+
+enum {
+    TLIB_OK = 0,
+    TLIB_EINVAL = 1,  /* null pointer, order out of range, extent < 1, stride < 0, p < 2 for TTV/TTM */
+    TLIB_ESHAPE = 2,  /* extents do not match the operation's shape rules */
+    TLIB_EMODE = 3,   /* a mode out of 1..p, or phi/psi/tau/layout not a permutation */
+    TLIB_EDTYPE = 4,  /* unsupported dtype, or operands / output of the wrong dtype */
+    TLIB_EALIAS = 5,  /* the output overlaps an input (add/scale may run in place, see there) */
+    TLIB_ESTRIDE = 6, /* the output's strides may map two multi-indices to one address */
+    TLIB_ENOMEM = 7,  /* the library's workspace could not be allocated */
+    TLIB_EHIP = 8     /* a HIP call or kernel launch failed */
+};
+
+typedef struct {
+    void* data;              /* device pointer to element (0,...,0) */
+    int32_t dtype;           /* tlib_dtype */
+    int32_t order;           /* p, 0 <= p <= TLIB_MAX_ORDER */
+    const int64_t* extents;  /* n[0..p-1], each >= 1 (host memory) */
+    const int64_t* strides;  /* w[0..p-1] in elements, or NULL (host memory) */
+    const int32_t* layout;   /* pi[0..p-1], 1-based, used when strides == NULL; NULL = first-order */
+} tlib_tensor;
+
+/* Mode-m tensor-times-vector, Sec. 5.2 Eq. ttv:
+ *   C(i_1..i_{m-1}, i_{m+1}..i_p) = sum_{i_m} A(i_1..i_p) * b(i_m).
+ * A: order p >= 2.  b: order 1, extent n_m, any stride.  C: order p-1 with the
+ * extents of A without n_m, in the mode order of A.  1 <= m <= p. */
+int tlib_ttv(const tlib_tensor* A, const tlib_tensor* b, int32_t m,
+             const tlib_tensor* C, void* stream);
+
+/* Mode-m tensor-times-matrix, Sec. 5.2 Eq. ttm:
+ *   C(i_1..i_{m-1}, j, i_{m+1}..i_p) = sum_{i_m} A(i_1..i_p) * B(j, i_m).
+ * A: order p >= 2.  B: order 2 with shape (n', n_m), any strides.
+ * C: order p, extents of A with n_m replaced by n'. */
+int tlib_ttm(const tlib_tensor* A, const tlib_tensor* B, int32_t m,
+             const tlib_tensor* C, void* stream);
+
+/* (q, phi, psi)-mode tensor-times-tensor, Sec. 5.2 Eq. ttt and ttt_indices.
+ * A has order q+r, B order q+s (r, s, q >= 0, q+r > 0, q+s > 0); phi (length
+ * q+r) and psi (length q+s) are 1-based permutations.  C has order r+s with
+ * n^c_k = n^a_{phi_k} (k <= r), n^c_{r+k} = n^b_{psi_k} (k <= s); the pairs
+ * (phi_{r+k}, psi_{s+k}), k = 1..q, are contracted and must have equal
+ * extents.  q = 0 is the outer product; r = s = 0 gives an order-0 C (one
+ * element) holding the inner product. */
+int tlib_ttt(const tlib_tensor* A, const tlib_tensor* B, int32_t q,
+             const int32_t* phi, const int32_t* psi,
+             const tlib_tensor* C, void* stream);
+
+/* Inner product <A, B> = sum_i A(i) B(i) (Sec. 5.2 Table 3) over equal shapes
+ * with independent layouts.  Accumulates in FP64 in a fixed order that only
+ * depends on the shapes and strides; writes one double to out_dev (device). */
+int tlib_inner(const tlib_tensor* A, const tlib_tensor* B, double* out_dev, void* stream);
+
+/* Frobenius norm sqrt(<A, A>) (Sec. 5.2 Table 3); one double to out_dev (device). */
+int tlib_norm(const tlib_tensor* A, double* out_dev, void* stream);
+
+/* C = alpha A + beta B (Sec. 5.1 Eq. transform with a scaled sum).  A, B, C
+ * have equal shapes and independent layouts and share one dtype.  C may be
+ * the same tensor as A or B (same data pointer and same strides); any other
+ * overlap is TLIB_EALIAS. */
+int tlib_add(double alpha, const tlib_tensor* A, double beta, const tlib_tensor* B,
+             const tlib_tensor* C, void* stream);
+
+/* C = alpha A (Sec. 5.1 Eq. scaling).  Equal shapes, independent layouts: with
+ * a different layout for C this is a relayout.  C may be A itself. */
+int tlib_scale(double alpha, const tlib_tensor* A, const tlib_tensor* C, void* stream);
+
+/* Transposition C = A^tau (Sec. 5.2 Table 3): C(i^c) = A(i^a) with
+ * i^c_r = i^a_{tau_r} and n^c_r = n^a_{tau_r}; tau is a 1-based permutation.
+ * Same dtype in and out; C must not overlap A. */
+int tlib_transpose(const tlib_tensor* A, const int32_t* tau, const tlib_tensor* C, void* stream);
+
+/* Stride tuple from shape and 1-based layout (Sec. 3.1 Eq. stride.tuple.permutation),
+ * layout NULL = first-order.  Host only; writes order values to strides_out. */
+int tlib_strides_from_layout(int32_t order, const int64_t* extents, const int32_t* layout,
+                             int64_t* strides_out);
+
+/* Message for the calling thread's last error ("" if none); the pointer stays
+ * valid until the thread's next tlib call. */
+const char* tlib_last_error(void);
+
+/* Static text for an error code. */
+const char* tlib_strerror(int code);
+
+/* Plan-only mode for the calling thread: when enabled, the entry points above
+ * validate and plan but launch nothing and touch no device; tlib_last_plan()
+ * then describes the kernel and the collapsed problem that would have run.
+ * Used to test the host logic without a GPU. */
+void tlib_set_plan_only(int enable);
+const char* tlib_last_plan(void);
+
+/* Library version string. */
+const char* tlib_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TLIB_H */

@@ -1,0 +1,714 @@
+// C-ABI entry points and host planner.
+//
+// Every entry point validates its descriptors, derives strides from layouts
+// (Sec. 3.1 Eq. stride.tuple.permutation), checks shapes against the defining
+// equation, then collapses the problem: dims of extent 1 are dropped and
+// neighbouring dims whose strides chain for every operand are merged, which
+// turns any dense layout into at most a few (extent, stride) pairs.  The
+// collapsed problem picks the kernel: TTV by its (lo, k, hi) regime, TTM/TTT
+// as one GEMM whose operands are addressed through per-group strides (no
+// unfolding, no transposed copy), inner/norm and add/scale/transpose as
+// streaming passes.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+
+#include "internal.hpp"
+
+namespace tlib {
+
+// ------------------------------------------------------------------ thread-local state
+
+static thread_local std::string g_err;
+static thread_local std::string g_plan;
+static thread_local bool g_plan_only = false;
+
+static int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+static void plan_note(const char* fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_plan = buf;
+}
+
+static const char* dname(int dt) {
+    switch (dt) {
+        case TLIB_F64: return "f64";
+        case TLIB_F32: return "f32";
+        case TLIB_BF16: return "bf16";
+        case TLIB_F16: return "f16";
+    }
+    return "?";
+}
+
+// ------------------------------------------------------------------ helpers
+
+FastDiv make_fastdiv(uint32_t d) {
+    FastDiv f;
+    f.d = d ? d : 1;
+    uint32_t s = 0;
+    while ((uint64_t(1) << s) < f.d) ++s;
+    f.s = s;
+    f.m = uint32_t(((uint64_t(1) << 32) * ((uint64_t(1) << s) - f.d)) / f.d + 1);
+    return f;
+}
+
+int coalesce(Dim* d, int nd, int nops, int key) {
+    int k = 0;
+    for (int i = 0; i < nd; ++i)
+        if (d[i].n != 1) d[k++] = d[i];
+    nd = k;
+    std::stable_sort(d, d + nd, [key, nops](const Dim& a, const Dim& b) {
+        if (a.s[key] != b.s[key]) return a.s[key] < b.s[key];
+        for (int o = 0; o < nops; ++o)
+            if (a.s[o] != b.s[o]) return a.s[o] < b.s[o];
+        return false;
+    });
+    int out = 0;
+    for (int i = 0; i < nd; ++i) {
+        if (out > 0) {
+            Dim& prev = d[out - 1];
+            bool chain = true;
+            for (int o = 0; o < nops; ++o)
+                if (d[i].s[o] != prev.s[o] * prev.n) chain = false;
+            if (chain) {
+                prev.n *= d[i].n;
+                continue;
+            }
+        }
+        d[out++] = d[i];
+    }
+    return out;
+}
+
+TileShape tile_shape(int t) {
+    switch (t) {
+        case GT_16x256: return {16, 256};
+        case GT_64x128: return {64, 128};
+        case GT_128x128: return {128, 128};
+        case GT_256x64: return {256, 64};
+        default: return {64, 64};
+    }
+}
+
+static bool fill_grp(Grp& g, const Dim* d, int nd, int o0, int o1) {
+    if (nd > GMAXD) return false;
+    g = Grp();
+    g.nd = nd;
+    g.total = 1;
+    for (int i = 0; i < nd; ++i) {
+        g.n[i] = d[i].n;
+        g.s0[i] = d[i].s[o0];
+        g.s1[i] = d[i].s[o1];
+        g.fd[i] = make_fastdiv(uint32_t(d[i].n));
+        g.total *= d[i].n;
+    }
+    return g.total < (int64_t(1) << 31);
+}
+
+static void fill_gdims(GDims& g, const Dim* d, int nd, int nops) {
+    g = GDims();
+    g.nd = nd;
+    g.total = 1;
+    for (int i = 0; i < nd; ++i) {
+        g.n[i] = d[i].n;
+        for (int o = 0; o < nops; ++o) g.s[o][i] = d[i].s[o];
+        g.total *= d[i].n;
+    }
+}
+
+static int normalize(const tlib_tensor* t, Ten& o, const char* name) {
+    if (!t) return fail(TLIB_EINVAL, "%s is NULL", name);
+    if (t->order < 0 || t->order > MAXP)
+        return fail(TLIB_EINVAL, "%s: order %d out of range 0..%d", name, t->order, MAXP);
+    if (t->dtype < TLIB_F64 || t->dtype > TLIB_F16)
+        return fail(TLIB_EDTYPE, "%s: unknown dtype %d", name, t->dtype);
+    if (!t->data) return fail(TLIB_EINVAL, "%s: data pointer is NULL", name);
+    if (t->order > 0 && !t->extents) return fail(TLIB_EINVAL, "%s: extents is NULL", name);
+    o.data = t->data;
+    o.dtype = t->dtype;
+    o.p = t->order;
+    for (int r = 0; r < o.p; ++r) {
+        if (t->extents[r] < 1) return fail(TLIB_EINVAL, "%s: extent n_%d = %lld < 1", name, r + 1,
+                                           (long long)t->extents[r]);
+        o.n[r] = t->extents[r];
+    }
+    if (t->strides) {
+        for (int r = 0; r < o.p; ++r) {
+            if (t->strides[r] < 0)
+                return fail(TLIB_EINVAL, "%s: stride w_%d < 0", name, r + 1);
+            o.w[r] = t->strides[r];
+        }
+    } else {
+        int32_t pi[MAXP];
+        for (int r = 0; r < o.p; ++r) pi[r] = t->layout ? t->layout[r] : r + 1;
+        bool seen[MAXP] = {};
+        for (int r = 0; r < o.p; ++r) {
+            if (pi[r] < 1 || pi[r] > o.p || seen[pi[r] - 1])
+                return fail(TLIB_EMODE, "%s: layout is not a permutation of 1..%d", name, o.p);
+            seen[pi[r] - 1] = true;
+        }
+        // Eq. stride.tuple.permutation: w_{pi_1} = 1, w_{pi_r} = prod_{q<r} n_{pi_q}
+        int64_t acc = 1;
+        for (int r = 0; r < o.p; ++r) {
+            o.w[pi[r] - 1] = acc;
+            acc *= o.n[pi[r] - 1];
+        }
+    }
+    // the largest element offset must fit comfortably in 62 bits
+    long double span = 0;
+    for (int r = 0; r < o.p; ++r) span += (long double)(o.n[r] - 1) * (long double)o.w[r];
+    if (span > 4.0e18L) return fail(TLIB_EINVAL, "%s: address range too large", name);
+    return TLIB_OK;
+}
+
+// Sufficient condition for distinct addresses: sorted by stride, every
+// stride is at least the previous stride times its extent.
+static bool injective(const Ten& t) {
+    Dim d[MAXP];
+    int nd = 0;
+    for (int r = 0; r < t.p; ++r)
+        if (t.n[r] > 1) d[nd++] = {t.n[r], {t.w[r], 0, 0}};
+    std::sort(d, d + nd, [](const Dim& a, const Dim& b) { return a.s[0] < b.s[0]; });
+    int64_t need = 1;
+    for (int i = 0; i < nd; ++i) {
+        if (d[i].s[0] < need) return false;
+        need = d[i].s[0] * d[i].n;
+    }
+    return true;
+}
+
+static void span(const Ten& t, uintptr_t& lo, uintptr_t& hi) {
+    int64_t last = 0;
+    for (int r = 0; r < t.p; ++r) last += (t.n[r] - 1) * t.w[r];
+    lo = uintptr_t(t.data);
+    hi = lo + uintptr_t((last + 1) * esize(t.dtype));
+}
+
+static bool overlaps(const Ten& a, const Ten& b) {
+    uintptr_t a0, a1, b0, b1;
+    span(a, a0, a1);
+    span(b, b0, b1);
+    return a0 < b1 && b0 < a1;
+}
+
+static bool same_view(const Ten& a, const Ten& b) {
+    if (a.data != b.data || a.p != b.p || a.dtype != b.dtype) return false;
+    for (int r = 0; r < a.p; ++r)
+        if (a.n[r] != b.n[r] || (a.n[r] > 1 && a.w[r] != b.w[r])) return false;
+    return true;
+}
+
+static int check_output(const Ten& c, const char* name) {
+    if (!injective(c))
+        return fail(TLIB_ESTRIDE, "%s: strides may map two multi-indices to one address", name);
+    return TLIB_OK;
+}
+
+// ------------------------------------------------------------------ workspace
+
+namespace {
+struct WsEntry {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_ws_mu;
+std::map<std::pair<int, hipStream_t>, WsEntry> g_ws;
+}  // namespace
+
+void* workspace(hipStream_t s, size_t bytes) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    WsEntry& e = g_ws[{dev, s}];
+    if (e.bytes >= bytes && e.ptr) return e.ptr;
+    if (e.ptr) {
+        // kernels already queued on this stream may still read the old buffer
+        if (hipStreamSynchronize(s) != hipSuccess) return nullptr;
+        (void)hipFree(e.ptr);
+        e.ptr = nullptr;
+        e.bytes = 0;
+    }
+    size_t want = std::max<size_t>(bytes, size_t(1) << 20);
+    void* p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    e.ptr = p;
+    e.bytes = want;
+    return p;
+}
+
+// ------------------------------------------------------------------ TTV planning
+
+static int run_ttv(const Ten& a, const Ten& b, int mi, const Ten& c, hipStream_t s) {
+    Dim d[MAXP];
+    int nd = 0;
+    for (int r = 0, k = 0; r < a.p; ++r) {
+        if (r == mi) continue;
+        d[nd++] = {a.n[r], {a.w[r], c.w[k], 0}};
+        ++k;
+    }
+    nd = coalesce(d, nd, 2, 0);
+
+    TtvParams P{};
+    P.A = a.data;
+    P.b = b.data;
+    P.C = c.data;
+    P.n_k = a.n[mi];
+    P.sA_k = a.w[mi];
+    P.sb = b.w[0];
+    P.n_lo = P.n_hi = 1;
+    P.sA_lo = P.sA_hi = P.sC_lo = P.sC_hi = 0;
+    int nlo = 0, nhi = 0;
+    for (int i = 0; i < nd; ++i) {
+        if (d[i].s[0] < P.sA_k || P.n_k == 1) {
+            if (nlo == 0 && nhi == 0) {
+                P.n_lo = d[i].n;
+                P.sA_lo = d[i].s[0];
+                P.sC_lo = d[i].s[1];
+            }
+            ++nlo;
+        } else {
+            if (nhi == 0) {
+                P.n_hi = d[i].n;
+                P.sA_hi = d[i].s[0];
+                P.sC_hi = d[i].s[1];
+            }
+            ++nhi;
+        }
+    }
+    // n_k == 1 puts every dim in "lo"; re-split so that at most one is lo
+    if (P.n_k == 1 && nlo == 2 && nhi == 0) {
+        P.n_hi = d[1].n;
+        P.sA_hi = d[1].s[0];
+        P.sC_hi = d[1].s[1];
+        nlo = 1;
+        nhi = 1;
+    }
+    const int64_t outs = P.n_lo * P.n_hi;
+    const bool fast = nlo <= 1 && nhi <= 1 && outs < (int64_t(1) << 31) && P.n_k < (int64_t(1) << 31);
+    const int es = esize(a.dtype);
+
+    if (fast && P.n_lo >= 32) {
+        const int maxvec = 16 / es;
+        auto vec_ok = [&](int v) {
+            if (v == 1) return true;
+            if (P.sA_lo != 1 || P.n_lo % v) return false;
+            if (P.n_k > 1 && P.sA_k % v) return false;
+            if (P.n_hi > 1 && P.sA_hi % v) return false;
+            return (uintptr_t(P.A) % (uintptr_t)(v * es)) == 0;
+        };
+        auto blocks = [&](int v) { return ((P.n_lo + 64 * v - 1) / (64 * v)) * P.n_hi; };
+        int vec = maxvec;
+        while (vec > 1 && !vec_ok(vec)) vec /= 2;
+        while (vec > 1 && blocks(vec) < 2048) vec /= 2;
+        int64_t nb = blocks(vec);
+        int ks = 1;
+        if (nb < 2048) {
+            int64_t want = (2048 + nb - 1) / nb;
+            int64_t maxk = std::max<int64_t>(1, P.n_k / 32);
+            ks = int(std::min<int64_t>(std::min<int64_t>(want, maxk), 64));
+        }
+        void* ws = nullptr;
+        size_t wsb = ks > 1 ? size_t(ks) * size_t(outs) * size_t(esize(acc_dtype(a.dtype))) : 0;
+        plan_note("ttv col dtype=%s n_lo=%lld n_k=%lld n_hi=%lld sA=(%lld,%lld,%lld) sC=(%lld,%lld) "
+                  "vec=%d ksplit=%d blocks=%lld",
+                  dname(a.dtype), (long long)P.n_lo, (long long)P.n_k, (long long)P.n_hi,
+                  (long long)P.sA_lo, (long long)P.sA_k, (long long)P.sA_hi, (long long)P.sC_lo,
+                  (long long)P.sC_hi, vec, ks, (long long)(nb * ks));
+        if (g_plan_only) return TLIB_OK;
+        if (ks > 1) {
+            ws = workspace(s, wsb);
+            if (!ws) return fail(TLIB_ENOMEM, "ttv: workspace of %zu bytes", wsb);
+        }
+        int rc = launch_ttv_col(a.dtype, P, vec, ks, ws, s);
+        return rc ? fail(rc, "ttv: launch failed") : TLIB_OK;
+    }
+    const bool slab_ok = fast && (P.n_lo == 1 || P.sA_lo == 1) && (P.n_k == 1 || P.sA_k == P.n_lo) &&
+                         (P.n_hi == 1 || P.sA_hi == P.n_lo * P.n_k);
+    if (slab_ok) {
+        const int64_t cap = 32768 / es;
+        const int64_t slab = P.n_lo * P.n_k;
+        int64_t S, kc;
+        if (slab <= cap) {
+            S = cap / slab;
+            kc = P.n_k;
+            // keep at least ~2048 blocks when the problem allows it
+            int64_t want_blocks = std::min<int64_t>(2048, P.n_hi);
+            int64_t smax = std::max<int64_t>(1, P.n_hi / want_blocks);
+            S = std::max<int64_t>(1, std::min(S, smax));
+        } else {
+            S = 1;
+            kc = std::max<int64_t>(1, cap / P.n_lo);
+        }
+        plan_note("ttv slab dtype=%s n_lo=%lld n_k=%lld n_hi=%lld sC=(%lld,%lld) slabs=%lld kc=%lld "
+                  "blocks=%lld",
+                  dname(a.dtype), (long long)P.n_lo, (long long)P.n_k, (long long)P.n_hi,
+                  (long long)P.sC_lo, (long long)P.sC_hi, (long long)S, (long long)kc,
+                  (long long)((P.n_hi + S - 1) / S));
+        if (g_plan_only) return TLIB_OK;
+        int rc = launch_ttv_slab(a.dtype, P, int(S), int(kc), s);
+        return rc ? fail(rc, "ttv: launch failed") : TLIB_OK;
+    }
+    GDims g;
+    fill_gdims(g, d, nd, 2);
+    plan_note("ttv generic dtype=%s dims=%d outputs=%lld n_k=%lld", dname(a.dtype), nd,
+              (long long)g.total, (long long)P.n_k);
+    if (g_plan_only) return TLIB_OK;
+    int rc = launch_ttv_generic(a.dtype, P, g, s);
+    return rc ? fail(rc, "ttv: launch failed") : TLIB_OK;
+}
+
+// ------------------------------------------------------------------ GEMM planning
+
+// dm: M-group dims with strides (X, C); dn: N-group (Y, C); dk: K-group (X, Y).
+static int run_gemm(int dtype, const void* X, const void* Y, void* C, Dim* dm, int ndm, Dim* dn,
+                    int ndn, Dim* dk, int ndk, const char* op, hipStream_t s) {
+    // Dims are stored with strides in slots 0/1 as documented above.
+    ndm = coalesce(dm, ndm, 2, 1);
+    ndn = coalesce(dn, ndn, 2, 1);
+    ndk = coalesce(dk, ndk, 2, 1);
+    int64_t M = 1, N = 1, K = 1;
+    for (int i = 0; i < ndm; ++i) M *= dm[i].n;
+    for (int i = 0; i < ndn; ++i) N *= dn[i].n;
+    for (int i = 0; i < ndk; ++i) K *= dk[i].n;
+
+    GemmParams P{};
+    bool fast = fill_grp(P.gm, dm, ndm, 0, 1) && fill_grp(P.gn, dn, ndn, 0, 1) &&
+                fill_grp(P.gk, dk, ndk, 0, 1);
+    if (fast) {
+        P.X = X;
+        P.Y = Y;
+        P.C = C;
+        P.M = int32_t(M);
+        P.N = int32_t(N);
+        P.K = int32_t(K);
+        auto minstride = [](const Dim* d, int nd, int o) {
+            int64_t m = INT64_MAX;
+            for (int i = 0; i < nd; ++i) m = std::min(m, d[i].s[o]);
+            return m;
+        };
+        P.x_kfast = ndk > 0 && (ndm == 0 || minstride(dk, ndk, 0) < minstride(dm, ndm, 0));
+        P.y_kfast = ndk > 0 && (ndn == 0 || minstride(dk, ndk, 1) < minstride(dn, ndn, 0));
+        int tile;
+        if (M <= 16) tile = GT_16x256;
+        else if (M <= 64) tile = GT_64x128;
+        else if (M <= 128) tile = GT_128x128;
+        else tile = GT_256x64;
+        auto ntiles = [&](int t) {
+            TileShape ts = tile_shape(t);
+            return ((M + ts.bm - 1) / ts.bm) * ((N + ts.bn - 1) / ts.bn);
+        };
+        if (ntiles(tile) < 1024 && tile != GT_16x256 && ntiles(GT_64x64) > ntiles(tile)) tile = GT_64x64;
+        TileShape ts = tile_shape(tile);
+        P.tiles_m = int32_t((M + ts.bm - 1) / ts.bm);
+        P.tiles_n = int32_t((N + ts.bn - 1) / ts.bn);
+        int64_t nt = int64_t(P.tiles_m) * P.tiles_n;
+        const int bk = (dtype == TLIB_F64 || dtype == TLIB_F32) ? 16 : 32;
+        int ks = 1;
+        if (nt < 1024) {
+            int64_t want = (1024 + nt - 1) / nt;
+            int64_t maxk = std::max<int64_t>(1, K / (4 * bk));
+            ks = int(std::min<int64_t>(std::min<int64_t>(want, maxk), 32));
+        }
+        P.ksplit = ks;
+        P.kchunk = int32_t(((K + ks - 1) / ks + bk - 1) / bk * bk);
+        if (ks > 1) P.ksplit = int((K + P.kchunk - 1) / P.kchunk);
+        size_t wsb = P.ksplit > 1 ? size_t(P.ksplit) * size_t(M) * size_t(N) *
+                                        size_t(esize(acc_dtype(dtype)))
+                                  : 0;
+        plan_note("%s gemm dtype=%s M=%lld N=%lld K=%lld dims=(%d,%d,%d) tile=%dx%d kfast=(%d,%d) "
+                  "ksplit=%d tiles=%lld",
+                  op, dname(dtype), (long long)M, (long long)N, (long long)K, ndm, ndn, ndk, ts.bm,
+                  ts.bn, P.x_kfast, P.y_kfast, P.ksplit, (long long)nt);
+        if (g_plan_only) return TLIB_OK;
+        if (P.ksplit > 1) {
+            P.part = workspace(s, wsb);
+            if (!P.part) return fail(TLIB_ENOMEM, "%s: workspace of %zu bytes", op, wsb);
+        }
+        int rc = launch_gemm(dtype, tile, P, s);
+        return rc ? fail(rc, "%s: launch failed", op) : TLIB_OK;
+    }
+    GDims gm, gn, gk;
+    fill_gdims(gm, dm, ndm, 2);
+    fill_gdims(gn, dn, ndn, 2);
+    fill_gdims(gk, dk, ndk, 2);
+    plan_note("%s generic dtype=%s M=%lld N=%lld K=%lld dims=(%d,%d,%d)", op, dname(dtype),
+              (long long)M, (long long)N, (long long)K, ndm, ndn, ndk);
+    if (g_plan_only) return TLIB_OK;
+    int rc = launch_gemm_generic(dtype, X, Y, C, gm, gn, gk, s);
+    return rc ? fail(rc, "%s: launch failed", op) : TLIB_OK;
+}
+
+static bool is_perm(int p, const int32_t* v) {
+    if (!v && p > 0) return false;
+    bool seen[MAXP] = {};
+    for (int r = 0; r < p; ++r) {
+        if (v[r] < 1 || v[r] > p || seen[v[r] - 1]) return false;
+        seen[v[r] - 1] = true;
+    }
+    return true;
+}
+
+static void begin_call() {
+    g_err.clear();
+    g_plan.clear();
+}
+
+}  // namespace tlib
+
+using namespace tlib;
+
+extern "C" {
+
+int tlib_ttv(const tlib_tensor* A, const tlib_tensor* b, int32_t m, const tlib_tensor* C,
+             void* stream) {
+    begin_call();
+    Ten a, v, c;
+    int rc;
+    if ((rc = normalize(A, a, "A")) || (rc = normalize(b, v, "b")) || (rc = normalize(C, c, "C")))
+        return rc;
+    if (a.p < 2) return fail(TLIB_EINVAL, "ttv: order of A must be >= 2 (got %d)", a.p);
+    if (m < 1 || m > a.p) return fail(TLIB_EMODE, "ttv: mode %d out of 1..%d", m, a.p);
+    const int mi = m - 1;
+    if (v.p != 1 || v.n[0] != a.n[mi])
+        return fail(TLIB_ESHAPE, "ttv: b must be a vector of length n_%d = %lld", m, (long long)a.n[mi]);
+    if (c.p != a.p - 1) return fail(TLIB_ESHAPE, "ttv: C must have order %d", a.p - 1);
+    for (int r = 0, k = 0; r < a.p; ++r) {
+        if (r == mi) continue;
+        if (c.n[k] != a.n[r]) return fail(TLIB_ESHAPE, "ttv: extent %d of C must be %lld", k + 1,
+                                          (long long)a.n[r]);
+        ++k;
+    }
+    if (v.dtype != a.dtype) return fail(TLIB_EDTYPE, "ttv: b must have A's dtype");
+    if (c.dtype != acc_dtype(a.dtype)) return fail(TLIB_EDTYPE, "ttv: C must be %s", dname(acc_dtype(a.dtype)));
+    if ((rc = check_output(c, "C"))) return rc;
+    if (overlaps(c, a) || overlaps(c, v)) return fail(TLIB_EALIAS, "ttv: C overlaps an input");
+    return run_ttv(a, v, mi, c, hipStream_t(stream));
+}
+
+int tlib_ttm(const tlib_tensor* A, const tlib_tensor* B, int32_t m, const tlib_tensor* C,
+             void* stream) {
+    begin_call();
+    Ten a, bm, c;
+    int rc;
+    if ((rc = normalize(A, a, "A")) || (rc = normalize(B, bm, "B")) || (rc = normalize(C, c, "C")))
+        return rc;
+    if (a.p < 2) return fail(TLIB_EINVAL, "ttm: order of A must be >= 2 (got %d)", a.p);
+    if (m < 1 || m > a.p) return fail(TLIB_EMODE, "ttm: mode %d out of 1..%d", m, a.p);
+    const int mi = m - 1;
+    if (bm.p != 2 || bm.n[1] != a.n[mi])
+        return fail(TLIB_ESHAPE, "ttm: B must have shape (n', n_%d = %lld)", m, (long long)a.n[mi]);
+    if (c.p != a.p) return fail(TLIB_ESHAPE, "ttm: C must have order %d", a.p);
+    for (int r = 0; r < a.p; ++r) {
+        int64_t want = r == mi ? bm.n[0] : a.n[r];
+        if (c.n[r] != want)
+            return fail(TLIB_ESHAPE, "ttm: extent %d of C must be %lld", r + 1, (long long)want);
+    }
+    if (bm.dtype != a.dtype) return fail(TLIB_EDTYPE, "ttm: B must have A's dtype");
+    if (c.dtype != acc_dtype(a.dtype)) return fail(TLIB_EDTYPE, "ttm: C must be %s", dname(acc_dtype(a.dtype)));
+    if ((rc = check_output(c, "C"))) return rc;
+    if (overlaps(c, a) || overlaps(c, bm)) return fail(TLIB_EALIAS, "ttm: C overlaps an input");
+    // GEMM roles: X = B (M = j), Y = A (N = the modes of A other than m), K = mode m.
+    Dim dm[1] = {{bm.n[0], {bm.w[0], c.w[mi], 0}}};
+    Dim dn[MAXP];
+    int ndn = 0;
+    for (int r = 0; r < a.p; ++r)
+        if (r != mi) dn[ndn++] = {a.n[r], {a.w[r], c.w[r], 0}};
+    Dim dk[1] = {{a.n[mi], {bm.w[1], a.w[mi], 0}}};
+    return run_gemm(a.dtype, bm.data, a.data, c.data, dm, 1, dn, ndn, dk, 1, "ttm", hipStream_t(stream));
+}
+
+int tlib_ttt(const tlib_tensor* A, const tlib_tensor* B, int32_t q, const int32_t* phi,
+             const int32_t* psi, const tlib_tensor* C, void* stream) {
+    begin_call();
+    Ten a, b, c;
+    int rc;
+    if ((rc = normalize(A, a, "A")) || (rc = normalize(B, b, "B")) || (rc = normalize(C, c, "C")))
+        return rc;
+    const int r = a.p - q, s = b.p - q;
+    if (q < 0 || r < 0 || s < 0) return fail(TLIB_EINVAL, "ttt: q=%d exceeds an operand order", q);
+    if (a.p == 0 || b.p == 0) return fail(TLIB_EINVAL, "ttt: q+r and q+s must be > 0");
+    if (!is_perm(a.p, phi)) return fail(TLIB_EMODE, "ttt: phi is not a permutation of 1..%d", a.p);
+    if (!is_perm(b.p, psi)) return fail(TLIB_EMODE, "ttt: psi is not a permutation of 1..%d", b.p);
+    if (c.p != r + s) return fail(TLIB_ESHAPE, "ttt: C must have order %d", r + s);
+    for (int k = 0; k < r; ++k)
+        if (c.n[k] != a.n[phi[k] - 1]) return fail(TLIB_ESHAPE, "ttt: extent %d of C mismatch", k + 1);
+    for (int k = 0; k < s; ++k)
+        if (c.n[r + k] != b.n[psi[k] - 1])
+            return fail(TLIB_ESHAPE, "ttt: extent %d of C mismatch", r + k + 1);
+    for (int k = 0; k < q; ++k)
+        if (a.n[phi[r + k] - 1] != b.n[psi[s + k] - 1])
+            return fail(TLIB_ESHAPE, "ttt: contracted pair %d has extents %lld and %lld", k + 1,
+                        (long long)a.n[phi[r + k] - 1], (long long)b.n[psi[s + k] - 1]);
+    if (b.dtype != a.dtype) return fail(TLIB_EDTYPE, "ttt: B must have A's dtype");
+    if (c.dtype != acc_dtype(a.dtype)) return fail(TLIB_EDTYPE, "ttt: C must be %s", dname(acc_dtype(a.dtype)));
+    if ((rc = check_output(c, "C"))) return rc;
+    if (overlaps(c, a) || overlaps(c, b)) return fail(TLIB_EALIAS, "ttt: C overlaps an input");
+    // GEMM roles: X = A (M = free A modes), Y = B (N = free B modes), K = pairs.
+    Dim dm[MAXP], dn[MAXP], dk[MAXP];
+    for (int k = 0; k < r; ++k) dm[k] = {a.n[phi[k] - 1], {a.w[phi[k] - 1], c.w[k], 0}};
+    for (int k = 0; k < s; ++k) dn[k] = {b.n[psi[k] - 1], {b.w[psi[k] - 1], c.w[r + k], 0}};
+    for (int k = 0; k < q; ++k) dk[k] = {a.n[phi[r + k] - 1], {a.w[phi[r + k] - 1], b.w[psi[s + k] - 1], 0}};
+    return run_gemm(a.dtype, a.data, b.data, c.data, dm, r, dn, s, dk, q, "ttt", hipStream_t(stream));
+}
+
+static int run_dot(const Ten& a, const Ten* b, double* out, bool sq, hipStream_t s, const char* op) {
+    Dim d[MAXP];
+    for (int r = 0; r < a.p; ++r) d[r] = {a.n[r], {a.w[r], b ? b->w[r] : a.w[r], 0}};
+    int nd = coalesce(d, a.p, 2, 0);
+    GDims g;
+    fill_gdims(g, d, nd, 2);
+    int np = dot_partials(g.total);
+    size_t wsb = size_t(np) * sizeof(double);
+    plan_note("%s dot dtype=%s dims=%d total=%lld partials=%d", op, dname(a.dtype), nd,
+              (long long)g.total, np);
+    if (g_plan_only) return TLIB_OK;
+    void* ws = workspace(s, wsb);
+    if (!ws) return fail(TLIB_ENOMEM, "%s: workspace", op);
+    int rc = launch_dot(a.dtype, a.data, b ? b->data : nullptr, g, out, sq, ws, wsb, s);
+    return rc ? fail(rc, "%s: launch failed", op) : TLIB_OK;
+}
+
+int tlib_inner(const tlib_tensor* A, const tlib_tensor* B, double* out_dev, void* stream) {
+    begin_call();
+    Ten a, b;
+    int rc;
+    if ((rc = normalize(A, a, "A")) || (rc = normalize(B, b, "B"))) return rc;
+    if (!out_dev) return fail(TLIB_EINVAL, "inner: out_dev is NULL");
+    if (a.p != b.p) return fail(TLIB_ESHAPE, "inner: orders differ");
+    for (int r = 0; r < a.p; ++r)
+        if (a.n[r] != b.n[r]) return fail(TLIB_ESHAPE, "inner: extent %d differs", r + 1);
+    if (a.dtype != b.dtype) return fail(TLIB_EDTYPE, "inner: dtypes differ");
+    return run_dot(a, &b, out_dev, false, hipStream_t(stream), "inner");
+}
+
+int tlib_norm(const tlib_tensor* A, double* out_dev, void* stream) {
+    begin_call();
+    Ten a;
+    int rc;
+    if ((rc = normalize(A, a, "A"))) return rc;
+    if (!out_dev) return fail(TLIB_EINVAL, "norm: out_dev is NULL");
+    return run_dot(a, nullptr, out_dev, true, hipStream_t(stream), "norm");
+}
+
+static int run_axpby(double alpha, const Ten& a, double beta, const Ten* b, const Ten& c,
+                     const int64_t* wA_by_c, hipStream_t s, const char* op) {
+    Dim d[MAXP];
+    // slot 1 holds B's strides; without B it repeats C's so that it never blocks a merge
+    for (int r = 0; r < c.p; ++r) d[r] = {c.n[r], {wA_by_c[r], b ? b->w[r] : c.w[r], c.w[r]}};
+    int nd = coalesce(d, c.p, 3, 2);
+    GDims g;
+    fill_gdims(g, d, nd, 3);
+    plan_note("%s ewise dtype=%s dims=%d total=%lld%s", op, dname(c.dtype), nd, (long long)g.total,
+              (nd == 1 && g.s[0][0] == 1 && g.s[2][0] == 1 && (!b || g.s[1][0] == 1)) ? " flat" : "");
+    if (g_plan_only) return TLIB_OK;
+    int rc = launch_axpby(c.dtype, alpha, a.data, beta, b ? b->data : nullptr, c.data, g, s);
+    return rc ? fail(rc, "%s: launch failed", op) : TLIB_OK;
+}
+
+int tlib_add(double alpha, const tlib_tensor* A, double beta, const tlib_tensor* B,
+             const tlib_tensor* C, void* stream) {
+    begin_call();
+    Ten a, b, c;
+    int rc;
+    if ((rc = normalize(A, a, "A")) || (rc = normalize(B, b, "B")) || (rc = normalize(C, c, "C")))
+        return rc;
+    if (a.p != b.p || a.p != c.p) return fail(TLIB_ESHAPE, "add: orders differ");
+    for (int r = 0; r < a.p; ++r)
+        if (a.n[r] != b.n[r] || a.n[r] != c.n[r]) return fail(TLIB_ESHAPE, "add: extent %d differs", r + 1);
+    if (a.dtype != b.dtype || a.dtype != c.dtype) return fail(TLIB_EDTYPE, "add: dtypes differ");
+    if ((rc = check_output(c, "C"))) return rc;
+    if ((overlaps(c, a) && !same_view(c, a)) || (overlaps(c, b) && !same_view(c, b)))
+        return fail(TLIB_EALIAS, "add: C overlaps an input without being that input");
+    return run_axpby(alpha, a, beta, &b, c, a.w, hipStream_t(stream), "add");
+}
+
+int tlib_scale(double alpha, const tlib_tensor* A, const tlib_tensor* C, void* stream) {
+    begin_call();
+    Ten a, c;
+    int rc;
+    if ((rc = normalize(A, a, "A")) || (rc = normalize(C, c, "C"))) return rc;
+    if (a.p != c.p) return fail(TLIB_ESHAPE, "scale: orders differ");
+    for (int r = 0; r < a.p; ++r)
+        if (a.n[r] != c.n[r]) return fail(TLIB_ESHAPE, "scale: extent %d differs", r + 1);
+    if (a.dtype != c.dtype) return fail(TLIB_EDTYPE, "scale: dtypes differ");
+    if ((rc = check_output(c, "C"))) return rc;
+    if (overlaps(c, a) && !same_view(c, a))
+        return fail(TLIB_EALIAS, "scale: C overlaps A without being A");
+    return run_axpby(alpha, a, 0.0, nullptr, c, a.w, hipStream_t(stream), "scale");
+}
+
+int tlib_transpose(const tlib_tensor* A, const int32_t* tau, const tlib_tensor* C, void* stream) {
+    begin_call();
+    Ten a, c;
+    int rc;
+    if ((rc = normalize(A, a, "A")) || (rc = normalize(C, c, "C"))) return rc;
+    if (!is_perm(a.p, tau)) return fail(TLIB_EMODE, "transpose: tau is not a permutation of 1..%d", a.p);
+    if (c.p != a.p) return fail(TLIB_ESHAPE, "transpose: orders differ");
+    int64_t wa[MAXP];
+    for (int r = 0; r < a.p; ++r) {
+        if (c.n[r] != a.n[tau[r] - 1])
+            return fail(TLIB_ESHAPE, "transpose: extent %d of C must be n_%d of A", r + 1, tau[r]);
+        wa[r] = a.w[tau[r] - 1];  // C(i^c) = A(i^a), i^c_r = i^a_{tau_r}
+    }
+    if (a.dtype != c.dtype) return fail(TLIB_EDTYPE, "transpose: dtypes differ");
+    if ((rc = check_output(c, "C"))) return rc;
+    if (overlaps(c, a)) return fail(TLIB_EALIAS, "transpose: C overlaps A");
+    return run_axpby(1.0, a, 0.0, nullptr, c, wa, hipStream_t(stream), "transpose");
+}
+
+int tlib_strides_from_layout(int32_t order, const int64_t* extents, const int32_t* layout,
+                             int64_t* strides_out) {
+    begin_call();
+    if (order < 0 || order > MAXP) return fail(TLIB_EINVAL, "order out of range");
+    if ((order > 0 && !extents) || !strides_out) return fail(TLIB_EINVAL, "NULL argument");
+    int64_t dummy = 0;
+    tlib_tensor t{&dummy, TLIB_F64, order, extents, nullptr, layout};
+    Ten o;
+    int rc = normalize(&t, o, "tensor");
+    if (rc) return rc;
+    for (int r = 0; r < order; ++r) strides_out[r] = o.w[r];
+    return TLIB_OK;
+}
+
+const char* tlib_last_error(void) { return g_err.c_str(); }
+
+const char* tlib_strerror(int code) {
+    switch (code) {
+        case TLIB_OK: return "ok";
+        case TLIB_EINVAL: return "invalid argument";
+        case TLIB_ESHAPE: return "shape mismatch";
+        case TLIB_EMODE: return "invalid mode or permutation";
+        case TLIB_EDTYPE: return "unsupported or mismatched dtype";
+        case TLIB_EALIAS: return "output overlaps an input";
+        case TLIB_ESTRIDE: return "output strides overlap";
+        case TLIB_ENOMEM: return "workspace allocation failed";
+        case TLIB_EHIP: return "HIP launch failed";
+    }
+    return "unknown error";
+}
+
+void tlib_set_plan_only(int enable) { g_plan_only = enable != 0; }
+const char* tlib_last_plan(void) { return g_plan.c_str(); }
+const char* tlib_version(void) { return "tlib-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,128 @@
+// Internal declarations shared by the host planner (plan.cpp, abi.cpp) and the
+// HIP kernels (k_*.hip).  Not part of the public ABI (see include/tlib.h).
+#pragma once
+
+#include <cstdint>
+#include <hip/hip_runtime_api.h>
+
+#include "../../include/tlib.h"
+
+namespace tlib {
+
+constexpr int MAXP = TLIB_MAX_ORDER;
+
+// ------------------------------------------------------------------ descriptors
+
+// A validated tensor: data pointer, dtype, order, extents and element strides.
+struct Ten {
+    void* data = nullptr;
+    int dtype = 0;
+    int p = 0;
+    int64_t n[MAXP] = {};
+    int64_t w[MAXP] = {};
+    int64_t numel() const {
+        int64_t s = 1;
+        for (int r = 0; r < p; ++r) s *= n[r];
+        return s;
+    }
+};
+
+inline int esize(int dtype) { return dtype == TLIB_F64 ? 8 : dtype == TLIB_F32 ? 4 : 2; }
+// Output dtype of a contraction: FP64 for FP64 input, FP32 otherwise.
+inline int acc_dtype(int dtype) { return dtype == TLIB_F64 ? TLIB_F64 : TLIB_F32; }
+
+// Unsigned 32-bit division by a run-time constant: q = (umulhi(x, m) + x) >> s
+// (round-up multiplier method, valid for every 32-bit x and divisor >= 1).
+struct FastDiv {
+    uint32_t d = 1, m = 1, s = 0;
+};
+FastDiv make_fastdiv(uint32_t d);
+
+// A dimension after coalescing, with the strides of up to three operands.
+struct Dim {
+    int64_t n;
+    int64_t s[3];
+};
+
+// Remove extent-1 dims, sort by the strides of operand `key` (ascending), and
+// merge neighbours i, i+1 whose strides chain for every operand
+// (s_op[i+1] == s_op[i] * n[i]).  Returns the new number of dims.
+int coalesce(Dim* d, int nd, int nops, int key);
+
+// Up to GMAXD dims of one index group (M, N or K of a GEMM, or the output
+// index of a streaming kernel) with the strides of two operands.
+constexpr int GMAXD = 4;
+struct Grp {
+    int nd = 0;
+    int64_t total = 1;
+    int64_t n[GMAXD] = {1, 1, 1, 1};
+    int64_t s0[GMAXD] = {};
+    int64_t s1[GMAXD] = {};
+    FastDiv fd[GMAXD];
+};
+
+// Up to MAXP dims for the generic (per-element decode) kernels; 64-bit divide.
+struct GDims {
+    int nd = 0;
+    int64_t total = 1;
+    int64_t n[MAXP] = {};
+    int64_t s[3][MAXP] = {};
+};
+
+// ------------------------------------------------------------------ kernel parameters
+
+// TTV on the collapsed (lo, k, hi) form: A(lo,k,hi) at lo*sA_lo + k*sA_k + hi*sA_hi.
+struct TtvParams {
+    const void* A;
+    const void* b;
+    void* C;
+    int64_t n_lo, n_k, n_hi;
+    int64_t sA_lo, sA_k, sA_hi, sb, sC_lo, sC_hi;
+};
+
+struct GemmParams {
+    const void* X;  // M x K operand
+    const void* Y;  // K x N operand
+    void* C;        // M x N result (or split-K partials)
+    int32_t M, N, K;
+    Grp gm;  // s0 = X stride, s1 = C stride
+    Grp gn;  // s0 = Y stride, s1 = C stride
+    Grp gk;  // s0 = X stride, s1 = Y stride
+    int32_t x_kfast, y_kfast;
+    int32_t tiles_m, tiles_n;
+    int32_t ksplit, kchunk;  // split-K: each z-slice handles kchunk of K
+    void* part;              // split-K partials [ksplit][M][N] (accumulator type)
+};
+
+enum GemmTile { GT_16x256 = 0, GT_64x128 = 1, GT_128x128 = 2, GT_256x64 = 3, GT_64x64 = 4, GT_COUNT };
+struct TileShape {
+    int bm, bn;
+};
+TileShape tile_shape(int t);
+
+// ------------------------------------------------------------------ launchers (k_*.hip)
+// Each returns TLIB_OK or TLIB_EHIP.
+int launch_ttv_col(int dtype, const TtvParams& p, int vec, int ksplit, void* ws, hipStream_t s);
+int launch_ttv_slab(int dtype, const TtvParams& p, int slabs, int kc, hipStream_t s);
+int launch_ttv_generic(int dtype, const TtvParams& p, const GDims& out, hipStream_t s);
+
+int launch_gemm(int dtype, int tile, const GemmParams& p, hipStream_t s);
+int launch_gemm_generic(int dtype, const void* X, const void* Y, void* C, const GDims& m,
+                        const GDims& n, const GDims& k, hipStream_t s);
+
+// Two-pass deterministic FP64 dot product over a GDims iteration space with
+// strides s[0] (A) and s[1] (B); B == nullptr means A . A.  `sqrt_out` takes
+// the square root of the final sum (norm).
+int launch_dot(int dtype, const void* A, const void* B, const GDims& d, double* out, bool sqrt_out,
+               void* ws, size_t ws_bytes, hipStream_t s);
+int dot_partials(int64_t total);  // number of first-pass partials for a given size
+
+// C = alpha*A + beta*B over GDims (strides s[0]=A, s[1]=B, s[2]=C); B may be null.
+int launch_axpby(int dtype, double alpha, const void* A, double beta, const void* B, void* C,
+                 const GDims& d, hipStream_t s);
+
+// ------------------------------------------------------------------ workspace (abi.cpp)
+// Per-(device, stream) scratch for reduction partials; grows on demand.
+void* workspace(hipStream_t s, size_t bytes);
+
+}  // namespace tlib

@@ -1,0 +1,172 @@
+// Streaming kernels: inner product / Frobenius norm (Sec. 5.2 Table 3) and
+// entrywise C = alpha A + beta B (Sec. 5.1 Eq. scaling, Eq. transform), which
+// also serves relayout and transposition (a permuted stride tuple for A).
+//
+// inner/norm: two passes with a fixed partition (a block per contiguous range
+// of the collapsed iteration space, a fixed shuffle/LDS tree inside the block,
+// then one block summing the partials in index order), so the FP64 result only
+// depends on the shapes and strides, never on scheduling.
+#include <algorithm>
+
+#include "device.hpp"
+
+namespace tlib {
+
+constexpr int DOT_BLOCK = 256;
+
+int dot_partials(int64_t total) {
+    int64_t np = (total + 65535) / 65536;
+    if (np < 1) np = 1;
+    if (np > 2048) np = 2048;
+    return int(np);
+}
+
+template <typename TI>
+__global__ __launch_bounds__(DOT_BLOCK) void dot_pass1(const TI* A, const TI* B, GDims g, int64_t chunk,
+                                                       double* part) {
+    const int tid = threadIdx.x;
+    const int64_t beg = int64_t(blockIdx.x) * chunk;
+    const int64_t end = min(g.total, beg + chunk);
+    const bool flat = g.nd <= 1 && g.s[0][0] == 1 && g.s[1][0] == 1;
+    double acc = 0.0;
+    if (flat) {
+        int64_t i = beg + tid;
+        for (; i + 3 * DOT_BLOCK < end; i += 4 * DOT_BLOCK) {
+            const double a0 = to_f64(A[i]), a1 = to_f64(A[i + DOT_BLOCK]);
+            const double a2 = to_f64(A[i + 2 * DOT_BLOCK]), a3 = to_f64(A[i + 3 * DOT_BLOCK]);
+            if (B) {
+                acc += a0 * to_f64(B[i]);
+                acc += a1 * to_f64(B[i + DOT_BLOCK]);
+                acc += a2 * to_f64(B[i + 2 * DOT_BLOCK]);
+                acc += a3 * to_f64(B[i + 3 * DOT_BLOCK]);
+            } else {
+                acc += a0 * a0;
+                acc += a1 * a1;
+                acc += a2 * a2;
+                acc += a3 * a3;
+            }
+        }
+        for (; i < end; i += DOT_BLOCK) {
+            const double a = to_f64(A[i]);
+            acc += a * (B ? to_f64(B[i]) : a);
+        }
+    } else {
+        for (int64_t i = beg + tid; i < end; i += DOT_BLOCK) {
+            int64_t off[2];
+            gd_decode(i, g, 2, off);
+            const double a = to_f64(A[off[0]]);
+            acc += a * (B ? to_f64(B[off[1]]) : a);
+        }
+    }
+    acc = warp_sum(acc, 64);
+    __shared__ double red[DOT_BLOCK / 64];
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+__global__ __launch_bounds__(DOT_BLOCK) void dot_pass2(const double* part, int np, double* out, int do_sqrt) {
+    const int tid = threadIdx.x;
+    double acc = 0.0;
+    for (int i = tid; i < np; i += DOT_BLOCK) acc += part[i];
+    acc = warp_sum(acc, 64);
+    __shared__ double red[DOT_BLOCK / 64];
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        const double s = ((red[0] + red[1]) + red[2]) + red[3];
+        out[0] = do_sqrt ? sqrt(s) : s;
+    }
+}
+
+template <typename TI>
+static int dot_launch(const void* A, const void* B, const GDims& g, double* out, bool sq, void* ws,
+                      hipStream_t s) {
+    const int np = dot_partials(g.total);
+    const int64_t chunk = (g.total + np - 1) / np;
+    hipLaunchKernelGGL((dot_pass1<TI>), dim3(np), dim3(DOT_BLOCK), 0, s, (const TI*)A, (const TI*)B, g, chunk,
+                       (double*)ws);
+    if (hipGetLastError() != hipSuccess) return TLIB_EHIP;
+    hipLaunchKernelGGL(dot_pass2, dim3(1), dim3(DOT_BLOCK), 0, s, (const double*)ws, np, out, sq ? 1 : 0);
+    return hipGetLastError() == hipSuccess ? TLIB_OK : TLIB_EHIP;
+}
+
+int launch_dot(int dtype, const void* A, const void* B, const GDims& d, double* out, bool sqrt_out, void* ws,
+               size_t ws_bytes, hipStream_t s) {
+    if (ws_bytes < size_t(dot_partials(d.total)) * sizeof(double)) return TLIB_ENOMEM;
+    switch (dtype) {
+        case TLIB_F64: return dot_launch<double>(A, B, d, out, sqrt_out, ws, s);
+        case TLIB_F32: return dot_launch<float>(A, B, d, out, sqrt_out, ws, s);
+        case TLIB_BF16: return dot_launch<bf16_t>(A, B, d, out, sqrt_out, ws, s);
+        case TLIB_F16: return dot_launch<f16_t>(A, B, d, out, sqrt_out, ws, s);
+    }
+    return TLIB_EDTYPE;
+}
+
+// ------------------------------------------------------------------ entrywise
+
+// Correct rounding of a double to a narrower type: round to odd into FP32
+// first (keeps a sticky bit), then round to nearest even into the target.
+__device__ __forceinline__ float to_f32_odd(double v) {
+    float f = float(v);
+    if (double(f) != v && f == f) {
+        uint32_t u = __float_as_uint(f);
+        if (fabs(double(f)) > fabs(v)) u -= 1;  // truncate toward zero
+        u |= 1u;
+        f = __uint_as_float(u);
+    }
+    return f;
+}
+
+template <typename TI> __device__ __forceinline__ TI round_out(double v);
+template <> __device__ __forceinline__ double round_out<double>(double v) { return v; }
+template <> __device__ __forceinline__ float round_out<float>(double v) { return float(v); }
+template <> __device__ __forceinline__ f16_t round_out<f16_t>(double v) { return f16_t(to_f32_odd(v)); }
+template <> __device__ __forceinline__ bf16_t round_out<bf16_t>(double v) {
+    const float f = to_f32_odd(v);
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return bf16_t{uint16_t((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u))};
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return bf16_t{uint16_t(u >> 16)};
+}
+
+template <typename TI>
+__global__ __launch_bounds__(256) void axpby_kernel(double alpha, const TI* A, double beta, const TI* B, TI* C,
+                                                    GDims g) {
+#pragma clang fp contract(off)
+    const bool flat = g.nd <= 1 && g.s[0][0] == 1 && g.s[2][0] == 1 && (!B || g.s[1][0] == 1);
+    const int64_t stride = int64_t(gridDim.x) * 256;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < g.total; i += stride) {
+        int64_t off[3];
+        if (flat) {
+            off[0] = off[1] = off[2] = i;
+        } else {
+            gd_decode(i, g, 3, off);
+        }
+        double v = alpha * to_f64(A[off[0]]);
+        if (B) v = v + beta * to_f64(B[off[1]]);
+        C[off[2]] = round_out<TI>(v);
+    }
+}
+
+template <typename TI>
+static int axpby_launch(double alpha, const void* A, double beta, const void* B, void* C, const GDims& g,
+                        hipStream_t s) {
+    const unsigned blocks = unsigned(std::max<int64_t>(1, std::min<int64_t>((g.total + 255) / 256, 8192)));
+    hipLaunchKernelGGL((axpby_kernel<TI>), dim3(blocks), dim3(256), 0, s, alpha, (const TI*)A, beta, (const TI*)B,
+                       (TI*)C, g);
+    return hipGetLastError() == hipSuccess ? TLIB_OK : TLIB_EHIP;
+}
+
+int launch_axpby(int dtype, double alpha, const void* A, double beta, const void* B, void* C, const GDims& d,
+                 hipStream_t s) {
+    switch (dtype) {
+        case TLIB_F64: return axpby_launch<double>(alpha, A, beta, B, C, d, s);
+        case TLIB_F32: return axpby_launch<float>(alpha, A, beta, B, C, d, s);
+        case TLIB_BF16: return axpby_launch<bf16_t>(alpha, A, beta, B, C, d, s);
+        case TLIB_F16: return axpby_launch<f16_t>(alpha, A, beta, B, C, d, s);
+    }
+    return TLIB_EDTYPE;
+}
+
+}  // namespace tlib

