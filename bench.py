@@ -1,0 +1,340 @@
+#!/usr/bin/env python3
+"""Throughput of the TTV / TTM / TTT contraction path on one MI355X.
+
+One step = one pass of the whole path over the order-p sweep (p = 3..7 at
+about 2^26 elements: 406^3, 90^4, 36^5, 20^6, 13^7), in first- and last-order
+layout, FP64 and FP32:
+  * TTV in every mode q (a dense n_q vector),
+  * TTM in every mode q with m x n_q matrices, m in {16, 64, 256},
+  * inner product and Frobenius norm (FP64 accumulation) and C = A + B on
+    every sweep tensor,
+plus the general TTT case: A (96,80,64,48) in first-order, last-order and
+(3,1,4,2) layout times B (64,48,120), contracting A{3,4} with B{1,2}, in FP32,
+BF16 and FP16 (FP32 accumulation).
+
+Inputs are resident in HBM before timing starts; each call alternates between
+two copies of its input tensor (several for the TTT operands) so that the
+256 MB Infinity Cache cannot serve a tensor the previous call just read.
+`value` is whole-step algorithmic throughput: the sum over all calls of the
+bytes the definitions require (every input read once, every output written
+once) divided by the step time.  Per-launch durations come from HIP events on
+the launch stream; the roofline object describes the kernel with the largest
+share of the step time.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "TTM/TTT TFLOP/s & TTV GB/s vs roofline; served p50/p99 latency, req/s"
+PEAK_HBM = 8.0e12
+PEAK_FLOPS = {"f64": 78.6e12, "f32": 157.3e12, "bf16": 2516.6e12, "f16": 2516.6e12}
+ESZ = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
+SWEEP = {3: 406, 4: 90, 5: 36, 6: 20, 7: 13}
+TTM_M = (16, 64, 256)
+
+
+class Case:
+    __slots__ = ("name", "family", "kernel", "bytes", "flops", "dtype", "fn", "ms")
+
+    def __init__(self, name, family, bytes_, flops, dtype, fn):
+        self.name, self.family, self.bytes, self.flops, self.dtype, self.fn = name, family, bytes_, flops, dtype, fn
+        self.kernel = None
+        self.ms = []
+
+    def ideal_s(self):
+        return max(self.bytes / PEAK_HBM, self.flops / PEAK_FLOPS[self.dtype])
+
+
+def _kernel_label(plan: str) -> str:
+    """Short kernel name from the library's plan string (op, kernel, dtype, tile/vec)."""
+    w = plan.split()
+    kv = dict(t.split("=", 1) for t in w[2:] if "=" in t)
+    lab = "%s %s %s" % (w[0], w[1], kv.get("dtype", "?"))
+    if "tile" in kv:
+        lab += " tile=" + kv["tile"]
+    if "vec" in kv:
+        lab += " vec=" + kv["vec"]
+    return lab
+
+
+def build_cases(T, torch, dev, quick=False):
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(171110912 + 1)
+    cases = []
+    keep = []  # tensors referenced by the closures
+    dtypes = ("f64", "f32")
+    ps = (3, 7) if quick else tuple(SWEEP)
+    # one output buffer per output dtype, sized for the largest TTM result
+    max_out = max(SWEEP[p] ** p // SWEEP[p] * max(TTM_M) for p in ps)
+    outbuf = {d: torch.empty(max_out, dtype=tdt[d], device=dev) for d in dtypes}
+
+    def out_view(d, shape, layout):
+        st = T.strides(shape, layout)
+        return torch.as_strided(outbuf[d], shape, st)
+
+    for d in dtypes:
+        s = ESZ[d]
+        for p in ps:
+            n = SWEEP[p]
+            shape = (n,) * p
+            N = n ** p
+            for lname, lay in (("first", list(range(1, p + 1))), ("last", list(range(p, 0, -1)))):
+                As = []
+                for c in range(2):
+                    A = T.empty(shape, lay, tdt[d], dev)
+                    A.copy_(torch.rand(shape, generator=gen, device=dev, dtype=tdt[d]).mul_(2).sub_(1))
+                    As.append(A)
+                keep.extend(As)
+                b = torch.rand(n, generator=gen, device=dev, dtype=tdt[d]).mul_(2).sub_(1)
+                Bm = {m: torch.rand(m, n, generator=gen, device=dev, dtype=tdt[d]).mul_(2).sub_(1) for m in TTM_M}
+                keep.append(b)
+                keep.extend(Bm.values())
+                for q in range(1, p + 1):
+                    A = As[q % 2]
+                    cshape = shape[: q - 1] + shape[q:]
+                    clay = [r if r < q else r - 1 for r in lay if r != q]
+                    C = out_view(d, cshape, clay)
+                    cases.append(Case("ttv p=%d %s q=%d %s" % (p, lname, q, d), "ttv", s * (N + n + N // n), 2 * N, d,
+                                      (lambda A=A, b=b, q=q, C=C: T.ttv(A, b, q, out=C))))
+                    cases[-1].kernel = _kernel_label(T.plan(T.ttv, A, b, q, out=C))
+                for q in range(1, p + 1):
+                    for m in TTM_M:
+                        A = As[(q + m) % 2]
+                        cshape = shape[: q - 1] + (m,) + shape[q:]
+                        C = out_view(d, cshape, lay)
+                        nb = s * (N + m * n) + s * (N // n * m)
+                        cases.append(Case("ttm p=%d %s q=%d m=%d %s" % (p, lname, q, m, d), "ttm", nb, 2 * N * m, d,
+                                          (lambda A=A, B=Bm[m], q=q, C=C: T.ttm(A, B, q, out=C))))
+                        cases[-1].kernel = _kernel_label(T.plan(T.ttm, A, Bm[m], q, out=C))
+                # inner / norm / add on the sweep tensor (FP64 accumulation)
+                res = torch.empty((), dtype=torch.float64, device=dev)
+                cases.append(Case("inner p=%d %s %s" % (p, lname, d), "inner", 2 * s * N, 2 * N, "f64",
+                                  (lambda A=As[0], B=As[1], r=res: T.inner(A, B, out=r))))
+                cases[-1].kernel = _kernel_label(T.plan(T.inner, As[0], As[1], out=res))
+                cases.append(Case("norm p=%d %s %s" % (p, lname, d), "norm", s * N, 2 * N, "f64",
+                                  (lambda A=As[1], r=res: T.norm(A, out=r))))
+                cases[-1].kernel = _kernel_label(T.plan(T.norm, As[1], out=res))
+                C = out_view(d, shape, lay)
+                cases.append(Case("add p=%d %s %s" % (p, lname, d), "add", 3 * s * N, 2 * N, d,
+                                  (lambda A=As[0], B=As[1], C=C: T.add(1.0, A, 1.0, B, out=C))))
+                cases[-1].kernel = _kernel_label(T.plan(T.add, 1.0, As[0], 1.0, As[1], out=C))
+                keep.append(res)
+
+    # TTT: A (96,80,64,48) x B (64,48,120), A{3,4} <-> B{1,2}
+    na, nbs = (96, 80, 64, 48), (64, 48, 120)
+    phi, psi = (1, 2, 3, 4), (3, 1, 2)
+    Mt, Nt, Kt = 96 * 80, 120, 64 * 48
+    for d in ("f32", "bf16", "f16"):
+        for lname, lay in (("first", (1, 2, 3, 4)), ("last", (4, 3, 2, 1)), ("perm3142", (3, 1, 4, 2))):
+            sets = []
+            for c in range(6 if not quick else 2):
+                A = T.empty(na, lay, tdt[d], dev)
+                A.copy_(torch.randn(na, generator=gen, device=dev, dtype=torch.float32).to(tdt[d]))
+                B = torch.randn(nbs, generator=gen, device=dev, dtype=torch.float32).to(tdt[d])
+                B = T.empty(nbs, None, tdt[d], dev).copy_(B)
+                C = T.empty((96, 80, 120), None, torch.float32, dev)
+                sets.append((A, B, C))
+            keep.extend(sets)
+            nbytes = ESZ[d] * (96 * 80 * 64 * 48 + 64 * 48 * 120) + 4 * Mt * Nt
+            for c, (A, B, C) in enumerate(sets):
+                cases.append(Case("ttt A=%s %s set=%d" % (lname, d, c), "ttt", nbytes, 2 * Mt * Nt * Kt, d,
+                                  (lambda A=A, B=B, C=C: T.ttt(A, B, 2, phi, psi, out=C))))
+                cases[-1].kernel = _kernel_label(T.plan(T.ttt, A, B, 2, phi, psi, out=C))
+    return cases, keep, outbuf
+
+
+def run_step(cases, torch, ev):
+    for i, c in enumerate(cases):
+        if ev is not None:
+            ev[i][0].record()
+        c.fn()
+        if ev is not None:
+            ev[i][1].record()
+
+
+def cpu_baseline(budget_s=15.0):
+    """The FP64 oracle on a bounded sample of the same sweep: TTV and TTM
+    (m=16) in mode 2 of the first-order p=3 (406^3) and p=5 (36^5) tensors,
+    then further modes until about `budget_s` seconds of CPU work."""
+    import numpy as np
+
+    import oracle
+    import synth
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+    plan = []
+    for p in (3, 5, 7, 4, 6):
+        for q in [2, 1, p] + [k for k in range(3, p)]:
+            for m in (None, 16, 64):
+                plan.append((p, q, m))
+    total_bytes = 0.0
+    spent = 0.0
+    done = []
+    tensors = {}
+    for p, q, m in plan:
+        if spent >= budget_s:
+            break
+        n = SWEEP[p]
+        if p not in tensors:
+            tensors[p] = oracle.materialize(synth.sweep_tensor(p))
+        A = tensors[p]
+        N = n ** p
+        g = synth.rng(1, 500 + p)
+        if m is None:
+            b = synth.uniform((n,), g)
+            t0 = time.perf_counter()
+            oracle.ttv(A, b, q)
+            dt = time.perf_counter() - t0
+            total_bytes += 8 * (N + n + N // n)
+            done.append("ttv p=%d q=%d" % (p, q))
+        else:
+            B = synth.uniform((m, n), g)
+            t0 = time.perf_counter()
+            oracle.ttm(A, B, q)
+            dt = time.perf_counter() - t0
+            total_bytes += 8 * (N + m * n) + 8 * (N // n * m)
+            done.append("ttm p=%d q=%d m=%d" % (p, q, m))
+        spent += dt
+    return {"value": total_bytes / spent / 1e9 if spent > 0 else None, "unit": "GB/s", "cores": threads,
+            "kind": "oracle", "seconds": round(spent, 2),
+            "sample": "FP64 oracle, first-order sweep tensors: " + ", ".join(done)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--quick", action="store_true", help="p = 3 and 7 only (for profiling runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cases-out", default="", help="write per-case timings (JSON lines) here")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only; --gpus %d is not supported "
+              "(the path would shard A along a free mode, see the design notes)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1711_10912_amd as T
+
+    dev = torch.device("cuda:0")
+    cases, keep, outbuf = build_cases(T, torch, dev, quick=args.quick)
+    torch.cuda.synchronize()
+    print("bench: %d calls per step" % len(cases), file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        run_step(cases, torch, None)
+    torch.cuda.synchronize()
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in cases]
+    step_ms = []
+    for k in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_step(cases, torch, ev)
+        torch.cuda.synchronize()
+        step_ms.append((time.perf_counter() - t0) * 1e3)
+        for i, c in enumerate(cases):
+            c.ms.append(ev[i][0].elapsed_time(ev[i][1]))
+        print("bench: step %d %.1f ms" % (k, step_ms[-1]), file=sys.stderr, flush=True)
+
+    ms_per_step = sum(step_ms) / len(step_ms)
+    tot_bytes = sum(c.bytes for c in cases)
+    tot_ideal = sum(c.ideal_s() for c in cases)
+
+    # per-kernel aggregation
+    kern = {}
+    for c in cases:
+        k = kern.setdefault(c.kernel, {"launches": 0, "ms": 0.0, "bytes": 0.0, "flops": 0.0, "t_hbm": 0.0,
+                                       "t_mfma": 0.0, "dtype": c.dtype, "family": c.family})
+        avg = sum(c.ms) / len(c.ms)
+        k["launches"] += 1
+        k["ms"] += avg
+        k["bytes"] += c.bytes
+        k["flops"] += c.flops
+        k["t_hbm"] += c.bytes / PEAK_HBM
+        k["t_mfma"] += c.flops / PEAK_FLOPS[c.dtype]
+    dom_name = max(kern, key=lambda n: kern[n]["ms"])
+    dk = kern[dom_name]
+    if dk["t_hbm"] >= dk["t_mfma"]:
+        achieved = dk["bytes"] / (dk["ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                "frac": round(achieved / 8000.0, 4)}
+    else:
+        achieved = dk["flops"] / (dk["ms"] * 1e-3) / 1e12
+        peak = PEAK_FLOPS[dk["dtype"]] / 1e12
+        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4)}
+    roof["traffic"] = None
+    roof["kernel"] = dom_name
+    roof["launches_per_step"] = dk["launches"]
+    roof["avg_launch_us"] = round(dk["ms"] * 1e3 / dk["launches"], 2)
+
+    fam = {}
+    for c in cases:
+        f = fam.setdefault(c.family, {"ms": 0.0, "bytes": 0.0, "flops": 0.0, "ideal_s": 0.0})
+        f["ms"] += sum(c.ms) / len(c.ms)
+        f["bytes"] += c.bytes
+        f["flops"] += c.flops
+        f["ideal_s"] += c.ideal_s()
+    breakdown = {}
+    for n, f in fam.items():
+        breakdown[n] = {"ms": round(f["ms"], 3), "GB/s": round(f["bytes"] / (f["ms"] * 1e-3) / 1e9, 1),
+                        "TFLOP/s": round(f["flops"] / (f["ms"] * 1e-3) / 1e12, 3),
+                        "roofline_frac": round(f["ideal_s"] / (f["ms"] * 1e-3), 4)}
+    kernels = {n: {"launches": k["launches"], "ms": round(k["ms"], 3),
+                   "GB/s": round(k["bytes"] / (k["ms"] * 1e-3) / 1e9, 1),
+                   "TFLOP/s": round(k["flops"] / (k["ms"] * 1e-3) / 1e12, 3),
+                   "roofline_frac": round(max(k["t_hbm"], k["t_mfma"]) / (k["ms"] * 1e-3), 4)}
+               for n, k in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])}
+
+    if args.cases_out:
+        with open(args.cases_out, "w") as f:
+            for c in cases:
+                avg = sum(c.ms) / len(c.ms)
+                f.write(json.dumps({"case": c.name, "kernel": c.kernel, "us": round(avg * 1e3, 2),
+                                    "GB/s": round(c.bytes / (avg * 1e-3) / 1e9, 1),
+                                    "TFLOP/s": round(c.flops / (avg * 1e-3) / 1e12, 3),
+                                    "roofline_frac": round(c.ideal_s() / (avg * 1e-3), 4)}) + "\n")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        del keep, outbuf
+        cpu = cpu_baseline()
+
+    out = {
+        "metric": METRIC,
+        "value": round(tot_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+        "unit": "GB/s (algorithmic bytes of the whole step / step time)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64,f32 (sweep); f32,bf16,f16 with f32 accumulation (ttt); f64 accumulation (inner/norm)",
+        "data": "synthetic (seeded uniform[-1,1] / normal(0,1) on device)",
+        "config": {"workload": "order-p sweep p=3..7 (406^3,90^4,36^5,20^6,13^7), every mode, first+last order, "
+                               "f64+f32: TTV, TTM m=16/64/256, inner, norm, add; plus TTT (96,80,64,48)x(64,48,120) "
+                               "A{3,4}<->B{1,2}, 3 A layouts, f32/bf16/f16" + (" [quick: p=3,7 only]" if args.quick else ""),
+                   "calls_per_step": len(cases)},
+        "roofline_frac_step": round(tot_ideal / (ms_per_step * 1e-3), 4),
+        "roofline": roof,
+        "breakdown": breakdown,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -103,6 +103,8 @@ TileShape tile_shape(int t) {
         case GT_64x128: return {64, 128};
         case GT_128x128: return {128, 128};
         case GT_256x64: return {256, 64};
+        case GT_128x64: return {128, 64};
+        case GT_256x32: return {256, 32};
         default: return {64, 64};
     }
 }
@@ -383,13 +385,33 @@ static int run_ttv(const Ten& a, const Ten& b, int mi, const Ten& c, hipStream_t
 static int run_gemm(int dtype, const void* X, const void* Y, void* C, Dim* dm, int ndm, Dim* dn,
                     int ndn, Dim* dk, int ndk, const char* op, hipStream_t s) {
     // Dims are stored with strides in slots 0/1 as documented above.
-    ndm = coalesce(dm, ndm, 2, 1);
-    ndn = coalesce(dn, ndn, 2, 1);
-    ndk = coalesce(dk, ndk, 2, 1);
     int64_t M = 1, N = 1, K = 1;
     for (int i = 0; i < ndm; ++i) M *= dm[i].n;
     for (int i = 0; i < ndn; ++i) N *= dn[i].n;
     for (int i = 0; i < ndk; ++i) K *= dk[i].n;
+    // Roles: the MFMA result puts consecutive columns of C in consecutive
+    // lanes, so the group holding C's unit-stride dim becomes N.
+    auto minstride = [](const Dim* d, int nd, int o) {
+        int64_t m = INT64_MAX;
+        for (int i = 0; i < nd; ++i)
+            if (d[i].n > 1) m = std::min(m, d[i].s[o]);
+        return m;
+    };
+    if (minstride(dm, ndm, 1) < minstride(dn, ndn, 1)) {
+        std::swap(X, Y);
+        std::swap(M, N);
+        Dim tmp[MAXP];
+        for (int i = 0; i < ndm; ++i) tmp[i] = dm[i];
+        for (int i = 0; i < ndn; ++i) dm[i] = dn[i];
+        for (int i = 0; i < ndm; ++i) dn[i] = tmp[i];
+        std::swap(ndm, ndn);
+        for (int i = 0; i < ndk; ++i) std::swap(dk[i].s[0], dk[i].s[1]);
+    }
+    ndm = coalesce(dm, ndm, 2, 1);
+    ndn = coalesce(dn, ndn, 2, 1);
+    // K is walked in the order of the larger operand's strides so that its
+    // loads run along memory.
+    ndk = coalesce(dk, ndk, 2, M > N ? 0 : 1);
 
     GemmParams P{};
     bool fast = fill_grp(P.gm, dm, ndm, 0, 1) && fill_grp(P.gn, dn, ndn, 0, 1) &&
@@ -401,28 +423,38 @@ static int run_gemm(int dtype, const void* X, const void* Y, void* C, Dim* dm, i
         P.M = int32_t(M);
         P.N = int32_t(N);
         P.K = int32_t(K);
-        auto minstride = [](const Dim* d, int nd, int o) {
-            int64_t m = INT64_MAX;
-            for (int i = 0; i < nd; ++i) m = std::min(m, d[i].s[o]);
-            return m;
-        };
+        {
+            // 16-byte stores along N: unit stride on N's first dim, runs of whole
+            // vectors in every dim, and a 16-byte aligned base.
+            const int v = 16 / esize(acc_dtype(dtype));
+            bool ok = ndn >= 1 && dn[0].s[1] == 1 && dn[0].n % v == 0 && (uintptr_t(C) % 16) == 0;
+            for (int i = 1; i < ndn; ++i) ok = ok && dn[i].s[1] % v == 0;
+            for (int i = 0; i < ndm; ++i) ok = ok && dm[i].s[1] % v == 0;
+            P.c_vec = ok ? 1 : 0;
+        }
         P.x_kfast = ndk > 0 && (ndm == 0 || minstride(dk, ndk, 0) < minstride(dm, ndm, 0));
         P.y_kfast = ndk > 0 && (ndn == 0 || minstride(dk, ndk, 1) < minstride(dn, ndn, 0));
-        int tile;
-        if (M <= 16) tile = GT_16x256;
-        else if (M <= 64) tile = GT_64x128;
-        else if (M <= 128) tile = GT_128x128;
-        else tile = GT_256x64;
+        // FP64 accumulators are twice as wide: keep a wave's tile at 64x32 so
+        // that two waves fit per SIMD.
+        const bool wide_acc = dtype == TLIB_F64;
         auto ntiles = [&](int t) {
             TileShape ts = tile_shape(t);
             return ((M + ts.bm - 1) / ts.bm) * ((N + ts.bn - 1) / ts.bn);
         };
+        int tile;
+        if (M <= 16) tile = GT_16x256;
+        else if (N <= 32) tile = GT_256x32;
+        else if (N <= 64) tile = wide_acc ? GT_256x32 : GT_256x64;
+        else if (M <= 64) tile = GT_64x128;
+        else if (M <= 128) tile = wide_acc ? GT_128x64 : GT_128x128;
+        else if (N <= 128) tile = wide_acc ? GT_128x64 : GT_128x128;
+        else tile = wide_acc ? GT_128x64 : GT_128x128;
         if (ntiles(tile) < 1024 && tile != GT_16x256 && ntiles(GT_64x64) > ntiles(tile)) tile = GT_64x64;
         TileShape ts = tile_shape(tile);
         P.tiles_m = int32_t((M + ts.bm - 1) / ts.bm);
         P.tiles_n = int32_t((N + ts.bn - 1) / ts.bn);
         int64_t nt = int64_t(P.tiles_m) * P.tiles_n;
-        const int bk = (dtype == TLIB_F64 || dtype == TLIB_F32) ? 16 : 32;
+        const int bk = dtype == TLIB_F64 ? 16 : 32;
         int ks = 1;
         if (nt < 1024) {
             int64_t want = (1024 + nt - 1) / nt;
@@ -436,9 +468,9 @@ static int run_gemm(int dtype, const void* X, const void* Y, void* C, Dim* dm, i
                                         size_t(esize(acc_dtype(dtype)))
                                   : 0;
         plan_note("%s gemm dtype=%s M=%lld N=%lld K=%lld dims=(%d,%d,%d) tile=%dx%d kfast=(%d,%d) "
-                  "ksplit=%d tiles=%lld",
+                  "cvec=%d ksplit=%d tiles=%lld",
                   op, dname(dtype), (long long)M, (long long)N, (long long)K, ndm, ndn, ndk, ts.bm,
-                  ts.bn, P.x_kfast, P.y_kfast, P.ksplit, (long long)nt);
+                  ts.bn, P.x_kfast, P.y_kfast, P.c_vec, P.ksplit, (long long)nt);
         if (g_plan_only) return TLIB_OK;
         if (P.ksplit > 1) {
             P.part = workspace(s, wsb);
@@ -527,6 +559,54 @@ int tlib_ttm(const tlib_tensor* A, const tlib_tensor* B, int32_t m, const tlib_t
     if (c.dtype != acc_dtype(a.dtype)) return fail(TLIB_EDTYPE, "ttm: C must be %s", dname(acc_dtype(a.dtype)));
     if ((rc = check_output(c, "C"))) return rc;
     if (overlaps(c, a) || overlaps(c, bm)) return fail(TLIB_EALIAS, "ttm: C overlaps an input");
+    // Short contraction: the streaming kernel (B resident in LDS, A streamed).
+    {
+        const int64_t Mr = bm.n[0], Kr = a.n[mi];
+        const int ks = ttm_stream_ks(a.dtype, int(std::min<int64_t>(Kr, 1 << 20)));
+        const int fm = Mr <= 16 ? 1 : Mr <= 64 ? 4 : Mr <= 256 ? 16 : 0;
+        Dim dn[MAXP];
+        int ndn = 0;
+        for (int r = 0; r < a.p; ++r)
+            if (r != mi) dn[ndn++] = {a.n[r], {a.w[r], c.w[r], 0}};
+        ndn = coalesce(dn, ndn, 2, 1);
+        TtmParams T{};
+        const bool wide = a.dtype == TLIB_BF16 || a.dtype == TLIB_F16;
+        const int kstep = wide ? 32 : 4;
+        const int64_t m16 = int64_t(fm) * 16, kp = int64_t(ks) * kstep;
+        const int64_t lds = wide ? m16 * (kp + 8) * 2 : kp * (m16 + (a.dtype == TLIB_F64 ? 4 : 16)) * esize(a.dtype);
+        int64_t cmin = INT64_MAX;
+        for (int i = 0; i < ndn; ++i) cmin = std::min(cmin, dn[i].s[1]);
+        const bool trans = Mr > 1 && c.w[mi] < cmin;
+        // Measured on MI355X over the order-p sweep: the streaming kernel wins
+        // whenever C is contiguous along j, for longer contractions, and for
+        // FP64 from k = 16; with k < 16, C strided along j and many rows the
+        // tiled GEMM's larger column runs win.
+        const bool prefer = trans || Kr >= 32 || (Kr >= 16 && a.dtype == TLIB_F64) ||
+                            (Mr <= 16 && a.dtype != TLIB_F64);
+        if (prefer && ks > 0 && fm > 0 && Kr <= 64 && lds <= 65536 && fill_grp(T.gn, dn, ndn, 0, 1)) {
+            T.X = bm.data;
+            T.Y = a.data;
+            T.C = c.data;
+            T.M = int32_t(Mr);
+            T.N = int32_t(T.gn.total);
+            T.K = int32_t(Kr);
+            T.sXm = bm.w[0];
+            T.sXk = bm.w[1];
+            T.sYk = a.w[mi];
+            T.sCm = c.w[mi];
+            const int64_t cols = fm >= 16 ? 64 : fm >= 4 ? 128 : 256;  // columns per workgroup tile
+            const int64_t tiles = (T.N + cols - 1) / cols;
+            const int per_cu = lds <= 20480 ? 4 : lds <= 40960 ? 3 : 2;
+            const int grid = int(std::max<int64_t>(1, std::min<int64_t>(tiles, 256 * per_cu)));
+            plan_note("ttm stream dtype=%s M=%lld N=%d K=%lld dims=%d fm=%d cols=%lld ks=%d trans=%d lds=%lld grid=%d "
+                      "tiles=%lld",
+                      dname(a.dtype), (long long)Mr, T.N, (long long)Kr, ndn, fm, (long long)cols, ks, trans ? 1 : 0,
+                      (long long)lds, grid, (long long)tiles);
+            if (g_plan_only) return TLIB_OK;
+            int rc2 = launch_ttm_stream(a.dtype, T, fm, ks, trans, grid, hipStream_t(stream));
+            return rc2 ? fail(rc2, "ttm: launch failed") : TLIB_OK;
+        }
+    }
     // GEMM roles: X = B (M = j), Y = A (N = the modes of A other than m), K = mode m.
     Dim dm[1] = {{bm.n[0], {bm.w[0], c.w[mi], 0}}};
     Dim dn[MAXP];

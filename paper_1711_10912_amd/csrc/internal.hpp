@@ -5,7 +5,7 @@
 #include <cstdint>
 #include <hip/hip_runtime_api.h>
 
-#include "../../include/tlib.h"
+#include "tlib.h"
 
 namespace tlib {
 
@@ -89,12 +89,27 @@ struct GemmParams {
     Grp gn;  // s0 = Y stride, s1 = C stride
     Grp gk;  // s0 = X stride, s1 = Y stride
     int32_t x_kfast, y_kfast;
+    int32_t c_vec;  // C rows can take 16-byte vector stores along N
     int32_t tiles_m, tiles_n;
     int32_t ksplit, kchunk;  // split-K: each z-slice handles kchunk of K
     void* part;              // split-K partials [ksplit][M][N] (accumulator type)
 };
 
-enum GemmTile { GT_16x256 = 0, GT_64x128 = 1, GT_128x128 = 2, GT_256x64 = 3, GT_64x64 = 4, GT_COUNT };
+// Streaming TTM with a short contraction: X = B (M x K, strides sXm, sXk),
+// Y = A (columns nu over gn, stride sYk along k), C(j, nu) at j*sCm + gn.s1.
+struct TtmParams {
+    const void* X;
+    const void* Y;
+    void* C;
+    int32_t M, N, K;
+    int64_t sXm, sXk, sYk, sCm;
+    Grp gn;  // s0 = Y stride, s1 = C stride
+};
+
+enum GemmTile {
+    GT_16x256 = 0, GT_64x128 = 1, GT_128x128 = 2, GT_256x64 = 3, GT_64x64 = 4, GT_128x64 = 5, GT_256x32 = 6,
+    GT_COUNT
+};
 struct TileShape {
     int bm, bn;
 };
@@ -107,6 +122,9 @@ int launch_ttv_slab(int dtype, const TtvParams& p, int slabs, int kc, hipStream_
 int launch_ttv_generic(int dtype, const TtvParams& p, const GDims& out, hipStream_t s);
 
 int launch_gemm(int dtype, int tile, const GemmParams& p, hipStream_t s);
+// fm: row blocks (1, 4 or 16); ks: k-steps from ttm_stream_ks (0 = unsupported)
+int launch_ttm_stream(int dtype, const TtmParams& p, int fm, int ks, bool trans, int grid, hipStream_t s);
+int ttm_stream_ks(int dtype, int k);
 int launch_gemm_generic(int dtype, const void* X, const void* Y, void* C, const GDims& m,
                         const GDims& n, const GDims& k, hipStream_t s);
 

@@ -29,6 +29,8 @@ typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
 
 template <typename TI> struct Mfma;
 
+// BK: depth of one K slice staged through LDS (several MFMA k-steps), chosen
+// so that a slice moves at least 8 KB per workgroup in flight.
 template <> struct Mfma<double> {
     using acc_t = d4_t;
     static constexpr int KSTEP = 4;
@@ -37,7 +39,7 @@ template <> struct Mfma<double> {
 template <> struct Mfma<float> {
     using acc_t = f4_t;
     static constexpr int KSTEP = 4;
-    static constexpr int BK = 16;
+    static constexpr int BK = 32;
 };
 template <> struct Mfma<bf16_t> {
     using acc_t = f4_t;
@@ -87,22 +89,42 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmParams P) {
     constexpr int FM = WM / 16, FN = WN / 16;
     // LDS row pitches (elements): k-major tiles for FP32/FP64 fragments,
     // m/n-major tiles (k contiguous) for the 16-bit fragments.
-    constexpr int PX = WIDE ? (BK + 8) : (BM + 4);
-    constexpr int PY = WIDE ? (BK + 8) : (BN + 4);
+    constexpr int PAD = sizeof(TI) == 8 ? 4 : 16;
+    constexpr int PX = WIDE ? (BK + 8) : (BM + PAD);
+    constexpr int PY = WIDE ? (BK + 8) : (BN + PAD);
     constexpr int XS = WIDE ? BM * PX : BK * PX;
     constexpr int YS = WIDE ? BN * PY : BK * PY;
     constexpr int EX = BM * BK / 256;  // X elements per thread per K slice
     constexpr int EY = BN * BK / 256;
     static_assert(EX >= 1 && EY >= 1, "tile too small");
 
-    __shared__ __align__(16) RT Xs[XS];
-    __shared__ __align__(16) RT Ys[YS];
+    // The X/Y slices and, after the K loop, the epilogue's staging rows share
+    // one LDS buffer.
+    constexpr int SP = WN + (sizeof(TA) == 8 ? 2 : 4);  // staging pitch, 16-byte rows
+    constexpr int XB = (XS * int(sizeof(RT)) + 15) / 16 * 16;
+    constexpr int MAIN_B = XB + YS * int(sizeof(RT));
+    constexpr int STAGE_B = 4 * 16 * SP * int(sizeof(TA));
+    __shared__ __align__(16) unsigned char smem[MAIN_B > STAGE_B ? MAIN_B : STAGE_B];
+    RT* Xs = reinterpret_cast<RT*>(smem);
+    RT* Ys = reinterpret_cast<RT*>(smem + XB);
+    // Offset tables: every row / column of the tile decoded once (-1 = outside),
+    // the K offsets of a slice decoded once per slice (double-buffered).
+    __shared__ int64_t xrow[BM], crow[BM], ycol[BN], ccol[BN];
+    __shared__ int64_t kx[2][BK], ky[2][BK];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WGM, wn = wave / WGM;
 
-    const int bid = blockIdx.x;
+    // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
+    // renumber them such that consecutive logical tiles (the M tiles that share
+    // one N tile of Y) run on the same XCD and meet in its L2.
+    int bid = blockIdx.x;
+    {
+        const int T = P.tiles_m * P.tiles_n;
+        const int xcd = bid & 7, idx = bid >> 3, per = T >> 3, rem = T & 7;
+        bid = (xcd < rem) ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+    }
     const int tm = bid % P.tiles_m, tn = bid / P.tiles_m;
     const int m0 = tm * BM, n0 = tn * BN;
     const int kz = blockIdx.y;
@@ -112,53 +134,71 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmParams P) {
     const TI* X = (const TI*)P.X;
     const TI* Y = (const TI*)P.Y;
 
-    // fixed per-thread element slots of the X and Y slices
-    int xm[EX], xk[EX], yn[EY], yk[EY];
-    int64_t xoff[EX], yoff[EY];
-#pragma unroll
-    for (int j = 0; j < EX; ++j) {
-        const int e = tid + j * 256;
-        if (P.x_kfast) { xk[j] = e % BK; xm[j] = e / BK; }
-        else { xm[j] = e % BM; xk[j] = e / BM; }
-        const int gm = m0 + xm[j];
-        xoff[j] = gm < P.M ? grp_off0(uint32_t(gm), P.gm) : int64_t(-1);
+    for (int i = tid; i < BM; i += 256) {
+        int64_t a = -1, c = -1;
+        if (m0 + i < P.M) grp_decode(uint32_t(m0 + i), P.gm, a, c);
+        xrow[i] = a;
+        crow[i] = c;
     }
-#pragma unroll
-    for (int j = 0; j < EY; ++j) {
-        const int e = tid + j * 256;
-        if (P.y_kfast) { yk[j] = e % BK; yn[j] = e / BK; }
-        else { yn[j] = e % BN; yk[j] = e / BN; }
-        const int gn = n0 + yn[j];
-        yoff[j] = gn < P.N ? grp_off0(uint32_t(gn), P.gn) : int64_t(-1);
+    for (int i = tid; i < BN; i += 256) {
+        int64_t a = -1, c = -1;
+        if (n0 + i < P.N) grp_decode(uint32_t(n0 + i), P.gn, a, c);
+        ycol[i] = a;
+        ccol[i] = c;
     }
+    auto ktable = [&](int k0, int slot) {
+        if (tid < BK) {
+            int64_t a = -1, b = -1;
+            if (k0 + tid < kend) grp_decode(uint32_t(k0 + tid), P.gk, a, b);
+            kx[slot][tid] = a;
+            ky[slot][tid] = b;
+        }
+    };
+
+    // Slot j of this thread in the X slice is element e = tid + 256 j, read
+    // along k (x_kfast) or along m; the same for Y.
+    auto xslot = [&](int j, int& mm, int& kk) {
+        const int e = tid + j * 256;
+        if (P.x_kfast) { kk = e % BK; mm = e / BK; }
+        else { mm = e % BM; kk = e / BM; }
+    };
+    auto yslot = [&](int j, int& nn, int& kk) {
+        const int e = tid + j * 256;
+        if (P.y_kfast) { kk = e % BK; nn = e / BK; }
+        else { nn = e % BN; kk = e / BN; }
+    };
 
     RT xr[EX], yr[EY];
-    auto fetch = [&](int k0) {
+    auto fetch = [&](int slot) {
 #pragma unroll
         for (int j = 0; j < EX; ++j) {
-            const int gk = k0 + xk[j];
-            RT v = RT(0);
-            if (xoff[j] >= 0 && gk < kend) v = raw_load(X + xoff[j] + grp_off0(uint32_t(gk), P.gk));
-            xr[j] = v;
+            int mm, kk;
+            xslot(j, mm, kk);
+            const int64_t a = xrow[mm], b = kx[slot][kk];
+            xr[j] = (a >= 0 && b >= 0) ? raw_load(X + a + b) : RT(0);
         }
 #pragma unroll
         for (int j = 0; j < EY; ++j) {
-            const int gk = k0 + yk[j];
-            RT v = RT(0);
-            if (yoff[j] >= 0 && gk < kend) v = raw_load(Y + yoff[j] + grp_off1(uint32_t(gk), P.gk));
-            yr[j] = v;
+            int nn, kk;
+            yslot(j, nn, kk);
+            const int64_t a = ycol[nn], b = ky[slot][kk];
+            yr[j] = (a >= 0 && b >= 0) ? raw_load(Y + a + b) : RT(0);
         }
     };
     auto stash = [&]() {
 #pragma unroll
         for (int j = 0; j < EX; ++j) {
-            if constexpr (WIDE) Xs[xm[j] * PX + xk[j]] = xr[j];
-            else Xs[xk[j] * PX + xm[j]] = xr[j];
+            int mm, kk;
+            xslot(j, mm, kk);
+            if constexpr (WIDE) Xs[mm * PX + kk] = xr[j];
+            else Xs[kk * PX + mm] = xr[j];
         }
 #pragma unroll
         for (int j = 0; j < EY; ++j) {
-            if constexpr (WIDE) Ys[yn[j] * PY + yk[j]] = yr[j];
-            else Ys[yk[j] * PY + yn[j]] = yr[j];
+            int nn, kk;
+            yslot(j, nn, kk);
+            if constexpr (WIDE) Ys[nn * PY + kk] = yr[j];
+            else Ys[kk * PY + nn] = yr[j];
         }
     };
 
@@ -171,11 +211,16 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmParams P) {
     const int rl = lane & 15, kq = lane >> 4;
     const int wm0 = wm * WM, wn0 = wn * WN;
 
-    if (kbeg < kend) fetch(kbeg);
+    ktable(kbeg, 0);
+    __syncthreads();
+    if (kbeg < kend) fetch(0);
+    int slot = 0;
     for (int k0 = kbeg; k0 < kend; k0 += BK) {
         stash();
+        if (k0 + BK < kend) ktable(k0 + BK, slot ^ 1);
         __syncthreads();
-        if (k0 + BK < kend) fetch(k0 + BK);
+        if (k0 + BK < kend) fetch(slot ^ 1);
+        slot ^= 1;
 #pragma unroll
         for (int ks = 0; ks < BK; ks += KSTEP) {
             if constexpr (WIDE) {
@@ -229,25 +274,42 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmParams P) {
         }
         return;
     }
+    // Staged epilogue: each wave writes one 16-row block of its tile to LDS,
+    // then stores whole rows with lanes running along C's columns (16-byte
+    // vector stores when C's column strides allow it).
     TA* C = (TA*)P.C;
-    int64_t rowoff[FM][4];
+    TA* stg = reinterpret_cast<TA*>(smem) + wave * 16 * SP;
+    constexpr int V = 16 / int(sizeof(TA));
+    constexpr int LPR = WN / V;   // lanes per staged row
+    constexpr int RPI = 64 / LPR;  // rows per pass
+    static_assert(WN % V == 0 && 64 % LPR == 0, "staging shape");
+    typedef uint32_t v16_t __attribute__((ext_vector_type(4)));
+    const int cl = (lane % LPR) * V;
+    const int64_t cb = ccol[wn0 + cl];
+    const bool vec = P.c_vec && cb >= 0;
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+    for (int i = 0; i < FM; ++i) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = m0 + wm0 + i * 16 + RQ * kq + RR * r;
-            rowoff[i][r] = row < P.M ? grp_off1(uint32_t(row), P.gm) : int64_t(-1);
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) stg[(RQ * kq + RR * r) * SP + j * 16 + rl] = acc[i][j][r];
+        __syncthreads();
+#pragma unroll
+        for (int rr = lane / LPR; rr < 16; rr += RPI) {
+            const int64_t ro = crow[wm0 + i * 16 + rr];
+            if (ro < 0) continue;
+            const TA* src = &stg[rr * SP + cl];
+            if (vec) {
+                *reinterpret_cast<v16_t*>(C + ro + cb) = *reinterpret_cast<const v16_t*>(src);
+            } else {
+#pragma unroll
+                for (int t = 0; t < V; ++t) {
+                    const int64_t co = ccol[wn0 + cl + t];
+                    if (co >= 0) C[ro + co] = src[t];
+                }
+            }
         }
-#pragma unroll
-    for (int j = 0; j < FN; ++j) {
-        const int col = n0 + wn0 + j * 16 + rl;
-        if (col >= P.N) continue;
-        const int64_t coff = grp_off1(uint32_t(col), P.gn);
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                if (rowoff[i][r] >= 0) C[rowoff[i][r] + coff] = acc[i][j][r];
+        __syncthreads();
     }
 }
 
@@ -308,6 +370,8 @@ static int gemm_dispatch(int tile, const GemmParams& p, hipStream_t s) {
         case GT_128x128: return gemm_launch<TI, 128, 128, 2, 2>(p, s);
         case GT_256x64: return gemm_launch<TI, 256, 64, 4, 1>(p, s);
         case GT_64x64: return gemm_launch<TI, 64, 64, 2, 2>(p, s);
+        case GT_128x64: return gemm_launch<TI, 128, 64, 2, 2>(p, s);
+        case GT_256x32: return gemm_launch<TI, 256, 32, 4, 1>(p, s);
     }
     return TLIB_EINVAL;
 }

@@ -91,7 +91,6 @@ def test_ttm_and_ttt_plans():
         A = _d((90, 90, 90, 90), _lib.F32)
         B = _d((64, 90), _lib.F32, ptr=FAKE * 2)
         C = _d((90, 64, 90, 90), _lib.F32, ptr=FAKE * 3)
-        assert _ttm(A, B, 2) if False else True
         assert _ttm(A, B, 2, C) == 0
         p = _plan()
         assert "gemm" in p and "M=64" in p and "K=90" in p and "N=729000" in p
@@ -103,7 +102,8 @@ def test_ttm_and_ttt_plans():
         rc = _lib.lib().tlib_ttt(ctypes.byref(Ad), ctypes.byref(Bd), 2, phi, psi, ctypes.byref(Cd), None)
         assert rc == 0
         p = _plan()
-        assert "M=7680" in p and "N=120" in p and "K=3072" in p and "dims=(2,1,2)" in p
+        # C is first-order, so its unit-stride mode (free A mode 1) becomes the GEMM's N side
+        assert "M=120" in p and "N=7680" in p and "K=3072" in p and "dims=(1,2,2)" in p
 
 
 def test_first_order_ttt_collapses_to_plain_gemm():

@@ -6,6 +6,7 @@ accumulation 2e-2 against the oracle on the original (unrounded) values and
 1e-5 against the oracle on the rounded inputs; integer-valued inputs must match
 bit for bit (every partial sum is exact)."""
 import itertools
+import zlib
 
 import numpy as np
 import pytest
@@ -34,14 +35,26 @@ def _layouts(p, g):
     return outs
 
 
+def _seed(*key):
+    return zlib.crc32(repr(key).encode()) % 1000
+
+
 def _check(got_t, ref_fn, X_inputs_rounded, X_inputs_orig, dtype, what):
-    """ref_fn(*inputs) -> oracle result (numpy array)."""
+    """ref_fn(*inputs) -> oracle result (numpy array).
+
+    16-bit inputs: the kernel is held to 1e-5 against the oracle on the same
+    rounded inputs; end to end (against the unrounded inputs) the error is
+    scaled by the same contraction over absolute values, |A|.|B|, which bounds
+    the rounding error of every dot product and stays meaningful when a
+    result cancels to almost zero."""
     got = to_np(got_t)
     ref = np.asarray(ref_fn(*X_inputs_rounded))
     if dtype in ("bf16", "f16"):
         assert_close(got, ref, TOL_KERNEL16, what + " (kernel)")
         ref0 = np.asarray(ref_fn(*X_inputs_orig))
-        assert_close(got, ref0, TOL[dtype], what + " (end to end)")
+        scale = np.linalg.norm(np.asarray(ref_fn(*[np.abs(x) for x in X_inputs_orig])).reshape(-1))
+        err = np.linalg.norm((got - ref0).reshape(-1)) / max(scale, 1e-300)
+        assert err <= TOL[dtype], "%s (end to end): error %.3e relative to |A||B| > %.1e" % (what, err, TOL[dtype])
     else:
         assert_close(got, ref, TOL[dtype], what)
 
@@ -65,7 +78,7 @@ TTV_SHAPES = [(37, 29), (70, 3, 41), (5, 67, 9), (13, 11, 9, 7), (3, 5, 2, 4, 6)
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("shape", TTV_SHAPES, ids=lambda s: "x".join(map(str, s)))
 def test_ttv_all_modes_layouts(T, dtype, shape):
-    g = synth.rng(10, hash((dtype,) + shape) % 1000)
+    g = synth.rng(10, _seed(dtype, shape))
     X = synth.uniform(shape, g)
     Xr = round_to(X, dtype)
     p = len(shape)
@@ -123,7 +136,7 @@ TTM_CASES = [((33, 29, 17), (1, 5, 16, 17, 64)), ((13, 11, 9, 7), (16, 64, 100))
 @pytest.mark.parametrize("case", TTM_CASES, ids=lambda c: "x".join(map(str, c[0])))
 def test_ttm_all_modes_layouts(T, dtype, case):
     shape, ms = case
-    g = synth.rng(13, hash((dtype,) + shape) % 1000)
+    g = synth.rng(13, _seed(dtype, shape))
     X = synth.uniform(shape, g)
     Xr = round_to(X, dtype)
     p = len(shape)
