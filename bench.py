@@ -151,6 +151,31 @@ def build_cases(T, torch, dev, quick=False):
     return cases, keep, outbuf
 
 
+def recorded_traffic(label):
+    """HBM bytes per launch for kernel `label` from a committed rocprofv3
+    summary under profiles/ (FETCH_SIZE and WRITE_SIZE, each scaled by the same
+    counter on a plain copy of known size), or None when no summary covers the
+    kernel or the kernel sources changed since the counters were taken."""
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1711_10912_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    sha = h.hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        kv = {}
+        with open(path) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith(("#", "-", "|", " ")):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("traffic_kernel") == label and kv.get("csrc_sha256") == sha:
+            return float(kv["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
+    return None, None
+
+
 def run_step(cases, torch, ev):
     for i, c in enumerate(cases):
         if ev is not None:
@@ -216,7 +241,20 @@ def main():
     ap.add_argument("--quick", action="store_true", help="p = 3 and 7 only (for profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cases-out", default="", help="write per-case timings (JSON lines) here")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (3 times), the reference for the "
+                         "FETCH_SIZE / WRITE_SIZE counter scale")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": 4 << 28, "launches": 3}))
+        return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus %d is not supported "
               "(the path would shard A along a free mode, see the design notes)" % args.gpus, file=sys.stderr)
@@ -273,7 +311,11 @@ def main():
         peak = PEAK_FLOPS[dk["dtype"]] / 1e12
         roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4)}
-    roof["traffic"] = None
+    tb, src = recorded_traffic(dom_name)
+    roof["traffic"] = round(tb / 1e9, 4) if tb is not None else None
+    roof["traffic_unit"] = "GB per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated)"
+    roof["traffic_source"] = src
+    roof["algorithmic_GB_per_launch"] = round(dk["bytes"] / dk["launches"] / 1e9, 4)
     roof["kernel"] = dom_name
     roof["launches_per_step"] = dk["launches"]
     roof["avg_launch_us"] = round(dk["ms"] * 1e3 / dk["launches"], 2)
