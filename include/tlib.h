@@ -24,7 +24,7 @@
  *
  * Data types.  A, B and b share one dtype.  Contractions write C in FP64 for
  * FP64 inputs and in FP32 for FP32, BF16 and FP16 inputs (accumulation in
- * FP64 resp. FP32).  add / scale / transpose keep the input dtype.  inner and
+ * FP64 resp. FP32).  add / transpose keep the input dtype, scale may convert.  inner and
  * norm accumulate and return FP64 for every input dtype.
  *
  * Ownership.  The caller owns every buffer.  The library never allocates or
@@ -119,7 +119,9 @@ int tlib_add(double alpha, const tlib_tensor* A, double beta, const tlib_tensor*
              const tlib_tensor* C, void* stream);
 
 /* C = alpha A (Sec. 5.1 Eq. scaling).  Equal shapes, independent layouts: with
- * a different layout for C this is a relayout.  C may be A itself. */
+ * a different layout for C this is a relayout.  C may have another dtype than
+ * A (a conversion, rounded once to nearest-even from the FP64 value alpha*A).
+ * C may be A itself (same pointer, strides and dtype). */
 int tlib_scale(double alpha, const tlib_tensor* A, const tlib_tensor* C, void* stream);
 
 /* Transposition C = A^tau (Sec. 5.2 Table 3): C(i^c) = A(i^a) with

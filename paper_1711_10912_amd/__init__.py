@@ -20,7 +20,7 @@ from ._lib import TlibError
 
 __all__ = [
     "ttv", "ttm", "ttt", "inner", "norm", "add", "scale", "transpose", "times_tensor",
-    "times_vectors", "strides", "layout_of", "empty", "TlibError", "plan",
+    "times_vectors", "strides", "layout_of", "empty", "TlibError", "plan", "hopm", "tucker",
 ]
 
 _torch = None
@@ -178,10 +178,11 @@ def add(alpha: float, A, beta: float, B, out=None, layout=None):
     return out
 
 
-def scale(alpha: float, A, out=None, layout=None):
-    """C = alpha A (Sec. 5.1 Eq. scaling); with another layout for C a relayout."""
+def scale(alpha: float, A, out=None, layout=None, dtype=None):
+    """C = alpha A (Sec. 5.1 Eq. scaling); with another layout for C a relayout,
+    with another dtype a conversion (rounded once, to nearest even)."""
     if out is None:
-        out = empty(A.shape, layout if layout is not None else layout_of(A), A.dtype, A.device)
+        out = empty(A.shape, layout if layout is not None else layout_of(A), dtype or A.dtype, A.device)
     _lib.check(_lib.lib().tlib_scale(float(alpha), ctypes.byref(_desc(A)), ctypes.byref(_desc(out)),
                                      _stream(A)))
     return out
@@ -222,3 +223,6 @@ def plan(fn, *args, **kwargs) -> str:
         L.tlib_set_plan_only(0)
         _plan_only = False
     return L.tlib_last_plan().decode()
+
+
+from .drivers import hopm, tucker  # noqa: E402

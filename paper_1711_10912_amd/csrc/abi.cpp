@@ -698,10 +698,10 @@ static int run_axpby(double alpha, const Ten& a, double beta, const Ten* b, cons
     int nd = coalesce(d, c.p, 3, 2);
     GDims g;
     fill_gdims(g, d, nd, 3);
-    plan_note("%s ewise dtype=%s dims=%d total=%lld%s", op, dname(c.dtype), nd, (long long)g.total,
+    plan_note("%s ewise dtype=%s->%s dims=%d total=%lld%s", op, dname(a.dtype), dname(c.dtype), nd, (long long)g.total,
               (nd == 1 && g.s[0][0] == 1 && g.s[2][0] == 1 && (!b || g.s[1][0] == 1)) ? " flat" : "");
     if (g_plan_only) return TLIB_OK;
-    int rc = launch_axpby(c.dtype, alpha, a.data, beta, b ? b->data : nullptr, c.data, g, s);
+    int rc = launch_axpby(a.dtype, c.dtype, alpha, a.data, beta, b ? b->data : nullptr, c.data, g, s);
     return rc ? fail(rc, "%s: launch failed", op) : TLIB_OK;
 }
 
@@ -730,9 +730,8 @@ int tlib_scale(double alpha, const tlib_tensor* A, const tlib_tensor* C, void* s
     if (a.p != c.p) return fail(TLIB_ESHAPE, "scale: orders differ");
     for (int r = 0; r < a.p; ++r)
         if (a.n[r] != c.n[r]) return fail(TLIB_ESHAPE, "scale: extent %d differs", r + 1);
-    if (a.dtype != c.dtype) return fail(TLIB_EDTYPE, "scale: dtypes differ");
     if ((rc = check_output(c, "C"))) return rc;
-    if (overlaps(c, a) && !same_view(c, a))
+    if (overlaps(c, a) && !(same_view(c, a) && a.dtype == c.dtype))
         return fail(TLIB_EALIAS, "scale: C overlaps A without being A");
     return run_axpby(alpha, a, 0.0, nullptr, c, a.w, hipStream_t(stream), "scale");
 }

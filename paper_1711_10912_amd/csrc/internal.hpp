@@ -136,8 +136,9 @@ int launch_dot(int dtype, const void* A, const void* B, const GDims& d, double* 
 int dot_partials(int64_t total);  // number of first-pass partials for a given size
 
 // C = alpha*A + beta*B over GDims (strides s[0]=A, s[1]=B, s[2]=C); B may be null.
-int launch_axpby(int dtype, double alpha, const void* A, double beta, const void* B, void* C,
-                 const GDims& d, hipStream_t s);
+// A and B have in_dtype; C has out_dtype (correctly rounded from FP64).
+int launch_axpby(int in_dtype, int out_dtype, double alpha, const void* A, double beta, const void* B,
+                 void* C, const GDims& d, hipStream_t s);
 
 // ------------------------------------------------------------------ workspace (abi.cpp)
 // Per-(device, stream) scratch for reduction partials; grows on demand.

@@ -130,8 +130,8 @@ template <> __device__ __forceinline__ bf16_t round_out<bf16_t>(double v) {
     return bf16_t{uint16_t(u >> 16)};
 }
 
-template <typename TI>
-__global__ __launch_bounds__(256) void axpby_kernel(double alpha, const TI* A, double beta, const TI* B, TI* C,
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void axpby_kernel(double alpha, const TI* A, double beta, const TI* B, TO* C,
                                                     GDims g) {
 #pragma clang fp contract(off)
     const bool flat = g.nd <= 1 && g.s[0][0] == 1 && g.s[2][0] == 1 && (!B || g.s[1][0] == 1);
@@ -145,26 +145,38 @@ __global__ __launch_bounds__(256) void axpby_kernel(double alpha, const TI* A, d
         }
         double v = alpha * to_f64(A[off[0]]);
         if (B) v = v + beta * to_f64(B[off[1]]);
-        C[off[2]] = round_out<TI>(v);
+        C[off[2]] = round_out<TO>(v);
     }
 }
 
-template <typename TI>
+template <typename TI, typename TO>
 static int axpby_launch(double alpha, const void* A, double beta, const void* B, void* C, const GDims& g,
                         hipStream_t s) {
     const unsigned blocks = unsigned(std::max<int64_t>(1, std::min<int64_t>((g.total + 255) / 256, 8192)));
-    hipLaunchKernelGGL((axpby_kernel<TI>), dim3(blocks), dim3(256), 0, s, alpha, (const TI*)A, beta, (const TI*)B,
-                       (TI*)C, g);
+    hipLaunchKernelGGL((axpby_kernel<TI, TO>), dim3(blocks), dim3(256), 0, s, alpha, (const TI*)A, beta,
+                       (const TI*)B, (TO*)C, g);
     return hipGetLastError() == hipSuccess ? TLIB_OK : TLIB_EHIP;
 }
 
-int launch_axpby(int dtype, double alpha, const void* A, double beta, const void* B, void* C, const GDims& d,
-                 hipStream_t s) {
-    switch (dtype) {
-        case TLIB_F64: return axpby_launch<double>(alpha, A, beta, B, C, d, s);
-        case TLIB_F32: return axpby_launch<float>(alpha, A, beta, B, C, d, s);
-        case TLIB_BF16: return axpby_launch<bf16_t>(alpha, A, beta, B, C, d, s);
-        case TLIB_F16: return axpby_launch<f16_t>(alpha, A, beta, B, C, d, s);
+template <typename TI>
+static int axpby_out(int out_dtype, double alpha, const void* A, double beta, const void* B, void* C,
+                     const GDims& d, hipStream_t s) {
+    switch (out_dtype) {
+        case TLIB_F64: return axpby_launch<TI, double>(alpha, A, beta, B, C, d, s);
+        case TLIB_F32: return axpby_launch<TI, float>(alpha, A, beta, B, C, d, s);
+        case TLIB_BF16: return axpby_launch<TI, bf16_t>(alpha, A, beta, B, C, d, s);
+        case TLIB_F16: return axpby_launch<TI, f16_t>(alpha, A, beta, B, C, d, s);
+    }
+    return TLIB_EDTYPE;
+}
+
+int launch_axpby(int in_dtype, int out_dtype, double alpha, const void* A, double beta, const void* B, void* C,
+                 const GDims& d, hipStream_t s) {
+    switch (in_dtype) {
+        case TLIB_F64: return axpby_out<double>(out_dtype, alpha, A, beta, B, C, d, s);
+        case TLIB_F32: return axpby_out<float>(out_dtype, alpha, A, beta, B, C, d, s);
+        case TLIB_BF16: return axpby_out<bf16_t>(out_dtype, alpha, A, beta, B, C, d, s);
+        case TLIB_F16: return axpby_out<f16_t>(out_dtype, alpha, A, beta, B, C, d, s);
     }
     return TLIB_EDTYPE;
 }

@@ -1,0 +1,38 @@
+"""Composite drivers over the C ABI: the higher-order power method and the
+Tucker (successive TTM) chain of Sec. 5.2.  These are host loops in the
+paper's order; every contraction, norm and scaling runs in the HIP kernels."""
+from __future__ import annotations
+
+from typing import List, Optional, Sequence, Tuple
+
+
+def hopm(A, us: Sequence, iters: int) -> Tuple[List[float], list]:
+    """Higher-order power method (Sec. 5.2): for each of `iters` sweeps and each
+    mode r, u_r <- A times every u_k (k != r, highest mode first);
+    lambda_r <- ||u_r|| (FP64); u_r <- u_r / lambda_r.  `us` are device vectors
+    of A's dtype.  Returns (lambdas, us) with lambdas as host floats."""
+    from . import norm, scale, times_vectors
+
+    us = [u.clone() for u in us]
+    lam = [0.0] * A.dim()
+    for _ in range(iters):
+        for r in range(A.dim()):
+            v = times_vectors(A, us, r + 1)
+            lam[r] = float(norm(v).item())
+            us[r] = scale(1.0 / lam[r], v, dtype=A.dtype)
+    return lam, us
+
+
+def tucker(A, Us: Sequence, stage_dtype=None):
+    """A x_1 U_1 x_2 U_2 ... (Sec. 5.2 tensor_times_matrices): successive mode-k
+    TTMs with factor matrices U_k of shape (r_k, n_k).  With `stage_dtype`
+    (e.g. torch.bfloat16) every intermediate is rounded to that dtype before it
+    enters the next TTM; results accumulate in FP32 (FP64 for FP64 data)."""
+    from . import scale, ttm
+
+    X = A
+    for k, U in enumerate(Us, start=1):
+        if stage_dtype is not None and X.dtype != stage_dtype:
+            X = scale(1.0, X, dtype=stage_dtype)
+        X = ttm(X, U, k)
+    return X
