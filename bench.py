@@ -176,6 +176,64 @@ def recorded_traffic(label):
     return None, None
 
 
+def served_workload(n_req, n_tensors, n_mats, cap, seed_case=0, device="cuda:0", rate=1e9):
+    """Materialise the served-stream workload on the device: a resident pool of
+    tensors (FP32 and BF16 copies, layouts as drawn), factor matrices, per-request
+    TTT operands and the request list (synth.served_stream)."""
+    import torch
+
+    import paper_1711_10912_amd as T
+    import synth
+
+    g = synth.rng(4, 10 + seed_case)
+    pools = synth.served_pools(n_tensors=n_tensors, n_mats=n_mats, cap=cap, g=g)
+    reqs = synth.served_stream(pools, n_req, rate, cap=cap, g=synth.rng(4, 20 + seed_case))
+    gen = torch.Generator(device=device)
+    gen.manual_seed(171110912 + 4 + seed_case)
+
+    def make(shape, layout, dt):
+        t = T.empty(shape, layout, dt, device)
+        t.copy_(torch.rand(tuple(shape), generator=gen, device=device, dtype=torch.float32).mul_(2).sub_(1))
+        return t
+
+    tens = {}
+    used = {r.a_id for r in reqs}
+    for i in sorted(used):
+        shape, lay = pools.tensors[i]
+        t32 = make(shape, list(lay), torch.float32)
+        tens[i] = {"f32": t32, "bf16": T.scale(1.0, t32, dtype=torch.bfloat16)}
+    mats = {}
+    for r in reqs:
+        if r.op == "ttm" and r.mat_id not in mats:
+            mm, nn = pools.matrices[r.mat_id]
+            m32 = make((mm, nn), None, torch.float32)
+            mats[r.mat_id] = {"f32": m32, "bf16": T.scale(1.0, m32, dtype=torch.bfloat16)}
+    vecs = {}
+    tttb = {}
+    for r in reqs:
+        shape = pools.tensors[r.a_id][0]
+        if r.op == "ttv":
+            n = shape[r.mode - 1]
+            if n not in vecs:
+                v32 = make((n,), None, torch.float32)
+                vecs[n] = {"f32": v32, "bf16": T.scale(1.0, v32, dtype=torch.bfloat16)}
+        elif r.op == "ttt":
+            b32 = make(r.b_shape, list(r.b_layout), torch.float32)
+            tttb[r.rid] = {"f32": b32, "bf16": T.scale(1.0, b32, dtype=torch.bfloat16)}
+
+    def operands(r, dt=None):
+        dt = dt or r.dtype
+        a = tens[r.a_id][dt]
+        if r.op == "ttv":
+            return a, vecs[pools.tensors[r.a_id][0][r.mode - 1]][dt]
+        if r.op == "ttm":
+            return a, mats[r.mat_id][dt]
+        return a, tttb[r.rid][dt]
+
+    torch.cuda.synchronize()
+    return reqs, operands
+
+
 def run_step(cases, torch, ev):
     for i, c in enumerate(cases):
         if ev is not None:

@@ -129,6 +129,32 @@ int tlib_scale(double alpha, const tlib_tensor* A, const tlib_tensor* C, void* s
  * Same dtype in and out; C must not overlap A. */
 int tlib_transpose(const tlib_tensor* A, const int32_t* tau, const tlib_tensor* C, void* stream);
 
+/* ---- Grouped launch of many small TTV / TTM requests ------------------------
+ * A request is a TTV (op 0, B = the vector b) or a TTM (op 1, B = the matrix)
+ * with the same argument rules as tlib_ttv / tlib_ttm.  tlib_batch_plan
+ * validates n requests and writes a work table into caller-provided host
+ * memory of tlib_batch_table_bytes(n) bytes; the caller copies the table to
+ * device memory and runs it with tlib_batch_run, which enqueues one kernel
+ * whose arguments depend only on the table's device address and the grid:
+ * the launch can be captured in a HIP graph once and replayed after the
+ * table's contents change.  Requests must not alias each other's outputs.
+ * A request whose tensors do not collapse to one (lo, k, hi) stride form is
+ * rejected with TLIB_ESTRIDE and its index in *bad (run it with tlib_ttv /
+ * tlib_ttm instead).  *units receives the number of 256-output work units. */
+typedef struct {
+    int32_t op;              /* 0 = TTV, 1 = TTM */
+    int32_t mode;            /* m, 1-based */
+    const tlib_tensor* A;
+    const tlib_tensor* B;
+    const tlib_tensor* C;
+} tlib_request;
+
+size_t tlib_batch_table_bytes(int32_t n);
+int tlib_batch_plan(const tlib_request* reqs, int32_t n, void* table_host, size_t table_bytes,
+                    int64_t* units, int32_t* bad);
+/* table_dev: device copy of a planned table; grid: persistent workgroups (0 = 1024). */
+int tlib_batch_run(const void* table_dev, int32_t grid, void* stream);
+
 /* Stride tuple from shape and 1-based layout (Sec. 3.1 Eq. stride.tuple.permutation),
  * layout NULL = first-order.  Host only; writes order values to strides_out. */
 int tlib_strides_from_layout(int32_t order, const int64_t* extents, const int32_t* layout,

@@ -17,8 +17,9 @@ MAX_ORDER = 16
 
 EXPORTS = (
     "tlib_ttv", "tlib_ttm", "tlib_ttt", "tlib_inner", "tlib_norm", "tlib_add", "tlib_scale",
-    "tlib_transpose", "tlib_strides_from_layout", "tlib_last_error", "tlib_strerror",
-    "tlib_set_plan_only", "tlib_last_plan", "tlib_version",
+    "tlib_transpose", "tlib_batch_table_bytes", "tlib_batch_plan", "tlib_batch_run",
+    "tlib_strides_from_layout", "tlib_last_error", "tlib_strerror", "tlib_set_plan_only",
+    "tlib_last_plan", "tlib_version",
 )
 
 
@@ -30,6 +31,16 @@ class TensorDesc(ctypes.Structure):
         ("extents", ctypes.POINTER(ctypes.c_int64)),
         ("strides", ctypes.POINTER(ctypes.c_int64)),
         ("layout", ctypes.POINTER(ctypes.c_int32)),
+    ]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [
+        ("op", ctypes.c_int32),
+        ("mode", ctypes.c_int32),
+        ("A", ctypes.POINTER(TensorDesc)),
+        ("B", ctypes.POINTER(TensorDesc)),
+        ("C", ctypes.POINTER(TensorDesc)),
     ]
 
 
@@ -62,6 +73,12 @@ def lib():
         L.tlib_scale.argtypes = [ctypes.c_double, P, P, vp]
         L.tlib_transpose.argtypes = [P, i32p, P, vp]
         L.tlib_strides_from_layout.argtypes = [ctypes.c_int32, i64p, i32p, i64p]
+        L.tlib_batch_table_bytes.argtypes = [ctypes.c_int32]
+        L.tlib_batch_table_bytes.restype = ctypes.c_size_t
+        L.tlib_batch_plan.argtypes = [ctypes.POINTER(Request), ctypes.c_int32, vp, ctypes.c_size_t, i64p, i32p]
+        L.tlib_batch_plan.restype = ctypes.c_int
+        L.tlib_batch_run.argtypes = [vp, ctypes.c_int32, vp]
+        L.tlib_batch_run.restype = ctypes.c_int
         for f in ("tlib_ttv", "tlib_ttm", "tlib_ttt", "tlib_inner", "tlib_norm", "tlib_add",
                   "tlib_scale", "tlib_transpose", "tlib_strides_from_layout"):
             getattr(L, f).restype = ctypes.c_int

@@ -490,6 +490,98 @@ static int run_gemm(int dtype, const void* X, const void* Y, void* C, Dim* dm, i
     return rc ? fail(rc, "%s: launch failed", op) : TLIB_OK;
 }
 
+static int check_ttv(const tlib_tensor* A, const tlib_tensor* b, int32_t m, const tlib_tensor* C, Ten& a,
+                     Ten& v, Ten& c) {
+    int rc;
+    if ((rc = normalize(A, a, "A")) || (rc = normalize(b, v, "b")) || (rc = normalize(C, c, "C")))
+        return rc;
+    if (a.p < 2) return fail(TLIB_EINVAL, "ttv: order of A must be >= 2 (got %d)", a.p);
+    if (m < 1 || m > a.p) return fail(TLIB_EMODE, "ttv: mode %d out of 1..%d", m, a.p);
+    const int mi = m - 1;
+    if (v.p != 1 || v.n[0] != a.n[mi])
+        return fail(TLIB_ESHAPE, "ttv: b must be a vector of length n_%d = %lld", m, (long long)a.n[mi]);
+    if (c.p != a.p - 1) return fail(TLIB_ESHAPE, "ttv: C must have order %d", a.p - 1);
+    for (int r = 0, k = 0; r < a.p; ++r) {
+        if (r == mi) continue;
+        if (c.n[k] != a.n[r]) return fail(TLIB_ESHAPE, "ttv: extent %d of C must be %lld", k + 1,
+                                          (long long)a.n[r]);
+        ++k;
+    }
+    if (v.dtype != a.dtype) return fail(TLIB_EDTYPE, "ttv: b must have A's dtype");
+    if (c.dtype != acc_dtype(a.dtype)) return fail(TLIB_EDTYPE, "ttv: C must be %s", dname(acc_dtype(a.dtype)));
+    if ((rc = check_output(c, "C"))) return rc;
+    if (overlaps(c, a) || overlaps(c, v)) return fail(TLIB_EALIAS, "ttv: C overlaps an input");
+    return TLIB_OK;
+}
+
+static int check_ttm(const tlib_tensor* A, const tlib_tensor* B, int32_t m, const tlib_tensor* C, Ten& a,
+                     Ten& bm, Ten& c) {
+    int rc;
+    if ((rc = normalize(A, a, "A")) || (rc = normalize(B, bm, "B")) || (rc = normalize(C, c, "C")))
+        return rc;
+    if (a.p < 2) return fail(TLIB_EINVAL, "ttm: order of A must be >= 2 (got %d)", a.p);
+    if (m < 1 || m > a.p) return fail(TLIB_EMODE, "ttm: mode %d out of 1..%d", m, a.p);
+    const int mi = m - 1;
+    if (bm.p != 2 || bm.n[1] != a.n[mi])
+        return fail(TLIB_ESHAPE, "ttm: B must have shape (n', n_%d = %lld)", m, (long long)a.n[mi]);
+    if (c.p != a.p) return fail(TLIB_ESHAPE, "ttm: C must have order %d", a.p);
+    for (int r = 0; r < a.p; ++r) {
+        int64_t want = r == mi ? bm.n[0] : a.n[r];
+        if (c.n[r] != want)
+            return fail(TLIB_ESHAPE, "ttm: extent %d of C must be %lld", r + 1, (long long)want);
+    }
+    if (bm.dtype != a.dtype) return fail(TLIB_EDTYPE, "ttm: B must have A's dtype");
+    if (c.dtype != acc_dtype(a.dtype)) return fail(TLIB_EDTYPE, "ttm: C must be %s", dname(acc_dtype(a.dtype)));
+    if ((rc = check_output(c, "C"))) return rc;
+    if (overlaps(c, a) || overlaps(c, bm)) return fail(TLIB_EALIAS, "ttm: C overlaps an input");
+    return TLIB_OK;
+}
+
+// Collapse one TTV (is_ttm false) or TTM request into a BatchItem.
+static bool batch_item(const Ten& a, const Ten& b, int mi, const Ten& c, bool is_ttm, BatchItem& it) {
+    Dim d[MAXP];
+    int nd = 0;
+    for (int r = 0, k = 0; r < a.p; ++r) {
+        if (r == mi) continue;
+        d[nd++] = {a.n[r], {a.w[r], is_ttm ? c.w[r] : c.w[k], 0}};
+        ++k;
+    }
+    nd = coalesce(d, nd, 2, 0);
+    it = BatchItem{};
+    it.dtype = a.dtype;
+    it.A = a.data;
+    it.B = b.data;
+    it.C = c.data;
+    it.n_k = a.n[mi];
+    it.sA_k = a.w[mi];
+    it.n_lo = it.n_hi = 1;
+    int nlo = 0, nhi = 0;
+    for (int i = 0; i < nd; ++i) {
+        if (nlo == 0 && nhi == 0 && (d[i].s[0] < it.sA_k || it.n_k == 1)) {
+            it.n_lo = d[i].n;
+            it.sA_lo = d[i].s[0];
+            it.sC_lo = d[i].s[1];
+            ++nlo;
+        } else {
+            if (nhi) return false;
+            it.n_hi = d[i].n;
+            it.sA_hi = d[i].s[0];
+            it.sC_hi = d[i].s[1];
+            ++nhi;
+        }
+    }
+    if (is_ttm) {
+        it.m = b.n[0];
+        it.sB_j = b.w[0];
+        it.sB_k = b.w[1];
+        it.sC_j = c.w[mi];
+    } else {
+        it.m = 1;
+        it.sB_k = b.w[0];
+    }
+    return true;
+}
+
 static bool is_perm(int p, const int32_t* v) {
     if (!v && p > 0) return false;
     bool seen[MAXP] = {};
@@ -515,50 +607,18 @@ int tlib_ttv(const tlib_tensor* A, const tlib_tensor* b, int32_t m, const tlib_t
              void* stream) {
     begin_call();
     Ten a, v, c;
-    int rc;
-    if ((rc = normalize(A, a, "A")) || (rc = normalize(b, v, "b")) || (rc = normalize(C, c, "C")))
-        return rc;
-    if (a.p < 2) return fail(TLIB_EINVAL, "ttv: order of A must be >= 2 (got %d)", a.p);
-    if (m < 1 || m > a.p) return fail(TLIB_EMODE, "ttv: mode %d out of 1..%d", m, a.p);
-    const int mi = m - 1;
-    if (v.p != 1 || v.n[0] != a.n[mi])
-        return fail(TLIB_ESHAPE, "ttv: b must be a vector of length n_%d = %lld", m, (long long)a.n[mi]);
-    if (c.p != a.p - 1) return fail(TLIB_ESHAPE, "ttv: C must have order %d", a.p - 1);
-    for (int r = 0, k = 0; r < a.p; ++r) {
-        if (r == mi) continue;
-        if (c.n[k] != a.n[r]) return fail(TLIB_ESHAPE, "ttv: extent %d of C must be %lld", k + 1,
-                                          (long long)a.n[r]);
-        ++k;
-    }
-    if (v.dtype != a.dtype) return fail(TLIB_EDTYPE, "ttv: b must have A's dtype");
-    if (c.dtype != acc_dtype(a.dtype)) return fail(TLIB_EDTYPE, "ttv: C must be %s", dname(acc_dtype(a.dtype)));
-    if ((rc = check_output(c, "C"))) return rc;
-    if (overlaps(c, a) || overlaps(c, v)) return fail(TLIB_EALIAS, "ttv: C overlaps an input");
-    return run_ttv(a, v, mi, c, hipStream_t(stream));
+    int rc = check_ttv(A, b, m, C, a, v, c);
+    if (rc) return rc;
+    return run_ttv(a, v, m - 1, c, hipStream_t(stream));
 }
 
 int tlib_ttm(const tlib_tensor* A, const tlib_tensor* B, int32_t m, const tlib_tensor* C,
              void* stream) {
     begin_call();
     Ten a, bm, c;
-    int rc;
-    if ((rc = normalize(A, a, "A")) || (rc = normalize(B, bm, "B")) || (rc = normalize(C, c, "C")))
-        return rc;
-    if (a.p < 2) return fail(TLIB_EINVAL, "ttm: order of A must be >= 2 (got %d)", a.p);
-    if (m < 1 || m > a.p) return fail(TLIB_EMODE, "ttm: mode %d out of 1..%d", m, a.p);
+    int rc = check_ttm(A, B, m, C, a, bm, c);
+    if (rc) return rc;
     const int mi = m - 1;
-    if (bm.p != 2 || bm.n[1] != a.n[mi])
-        return fail(TLIB_ESHAPE, "ttm: B must have shape (n', n_%d = %lld)", m, (long long)a.n[mi]);
-    if (c.p != a.p) return fail(TLIB_ESHAPE, "ttm: C must have order %d", a.p);
-    for (int r = 0; r < a.p; ++r) {
-        int64_t want = r == mi ? bm.n[0] : a.n[r];
-        if (c.n[r] != want)
-            return fail(TLIB_ESHAPE, "ttm: extent %d of C must be %lld", r + 1, (long long)want);
-    }
-    if (bm.dtype != a.dtype) return fail(TLIB_EDTYPE, "ttm: B must have A's dtype");
-    if (c.dtype != acc_dtype(a.dtype)) return fail(TLIB_EDTYPE, "ttm: C must be %s", dname(acc_dtype(a.dtype)));
-    if ((rc = check_output(c, "C"))) return rc;
-    if (overlaps(c, a) || overlaps(c, bm)) return fail(TLIB_EALIAS, "ttm: C overlaps an input");
     // Short contraction: the streaming kernel (B resident in LDS, A streamed).
     {
         const int64_t Mr = bm.n[0], Kr = a.n[mi];
@@ -753,6 +813,58 @@ int tlib_transpose(const tlib_tensor* A, const int32_t* tau, const tlib_tensor* 
     if ((rc = check_output(c, "C"))) return rc;
     if (overlaps(c, a)) return fail(TLIB_EALIAS, "transpose: C overlaps A");
     return run_axpby(1.0, a, 0.0, nullptr, c, wa, hipStream_t(stream), "transpose");
+}
+
+size_t tlib_batch_table_bytes(int32_t n) {
+    return sizeof(BatchHeader) + size_t(n < 0 ? 0 : n) * sizeof(BatchItem);
+}
+
+int tlib_batch_plan(const tlib_request* reqs, int32_t n, void* table_host, size_t table_bytes,
+                    int64_t* units, int32_t* bad) {
+    begin_call();
+    if (bad) *bad = -1;
+    if (n < 0 || (n > 0 && !reqs) || !table_host) return fail(TLIB_EINVAL, "batch: NULL argument");
+    if (table_bytes < tlib_batch_table_bytes(n)) return fail(TLIB_EINVAL, "batch: table too small");
+    BatchHeader* hdr = (BatchHeader*)table_host;
+    BatchItem* items = (BatchItem*)((char*)table_host + sizeof(BatchHeader));
+    int64_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        Ten a, b, c;
+        const bool is_ttm = reqs[i].op == 1;
+        if (reqs[i].op != 0 && reqs[i].op != 1) {
+            if (bad) *bad = i;
+            return fail(TLIB_EINVAL, "batch: request %d has unknown op %d", i, reqs[i].op);
+        }
+        int rc = is_ttm ? check_ttm(reqs[i].A, reqs[i].B, reqs[i].mode, reqs[i].C, a, b, c)
+                        : check_ttv(reqs[i].A, reqs[i].B, reqs[i].mode, reqs[i].C, a, b, c);
+        if (rc) {
+            if (bad) *bad = i;
+            return rc;
+        }
+        if (!batch_item(a, b, reqs[i].mode - 1, c, is_ttm, items[i])) {
+            if (bad) *bad = i;
+            return fail(TLIB_ESTRIDE, "batch: request %d does not collapse to one (lo, k, hi) form", i);
+        }
+        items[i].unit_begin = total;
+        total += (items[i].n_lo * items[i].m * items[i].n_hi + 255) / 256;
+    }
+    hdr->n_items = n;
+    hdr->total_units = total;
+    if (units) *units = total;
+    plan_note("batch items=%d units=%lld", n, (long long)total);
+    return TLIB_OK;
+}
+
+int tlib_batch_run(const void* table_dev, int32_t grid, void* stream) {
+    begin_call();
+    if (!table_dev) return fail(TLIB_EINVAL, "batch: table is NULL");
+    if (grid < 0) return fail(TLIB_EINVAL, "batch: grid < 0");
+    if (g_plan_only) {
+        plan_note("batch run grid=%d", grid ? grid : 1024);
+        return TLIB_OK;
+    }
+    int rc = launch_batch(table_dev, grid ? grid : 1024, hipStream_t(stream));
+    return rc ? fail(rc, "batch: launch failed") : TLIB_OK;
 }
 
 int tlib_strides_from_layout(int32_t order, const int64_t* extents, const int32_t* layout,

@@ -106,6 +106,25 @@ struct TtmParams {
     Grp gn;  // s0 = Y stride, s1 = C stride
 };
 
+// Work table of a grouped launch (k_batch.hip): a header followed by items.
+struct BatchHeader {
+    int32_t n_items;
+    int32_t pad0;
+    int64_t total_units;  // units of 256 outputs over all items
+    int64_t pad1[2];
+};
+struct BatchItem {
+    int32_t dtype;  // input dtype; C is FP64 for FP64 input, FP32 otherwise
+    int32_t pad0;
+    int64_t unit_begin;  // first unit of this item (prefix sum)
+    const void* A;
+    const void* B;
+    void* C;
+    int64_t n_lo, n_k, n_hi, m;  // TTV: m = 1
+    int64_t sA_lo, sA_k, sA_hi, sB_j, sB_k, sC_lo, sC_j, sC_hi;
+};
+int launch_batch(const void* table_dev, int grid, hipStream_t s);
+
 enum GemmTile {
     GT_16x256 = 0, GT_64x128 = 1, GT_128x128 = 2, GT_256x64 = 3, GT_64x64 = 4, GT_128x64 = 5, GT_256x32 = 6,
     GT_COUNT

@@ -177,12 +177,16 @@ def served_pools(n_tensors: int = 1024, n_mats: int = 256, cap: int = 1 << 24,
                  g: Optional[np.random.Generator] = None) -> ServedPools:
     g = g or rng(4, 0)
     pools = ServedPools()
+    # the smallest order-p tensor has 8^p elements: never draw an order the cap excludes
+    pmax = max(2, min(6, int(math.floor(math.log(cap) / math.log(8) + 1e-9))))
     for _ in range(n_tensors):
-        p = int(g.integers(2, 7))
-        while True:
+        p = int(g.integers(2, pmax + 1))
+        for _attempt in range(10000):
             shape = tuple(_log_uniform_int(g, 8, 512) for _ in range(p))
             if int(np.prod(shape, dtype=np.int64)) <= cap:
                 break
+        else:
+            shape = (8,) * p
         u = g.uniform()
         if u < 0.4:
             lay = tuple(range(1, p + 1))
