@@ -155,6 +155,46 @@ int tlib_batch_plan(const tlib_request* reqs, int32_t n, void* table_host, size_
 /* table_dev: device copy of a planned table; grid: persistent workgroups (0 = 1024). */
 int tlib_batch_run(const void* table_dev, int32_t grid, void* stream);
 
+/* ---- Request server (continuous batching on one GPU) ------------------------
+ * tlib_server_create starts a scheduler thread with `slots` HIP streams and an
+ * output arena of `output_budget` bytes of device memory (the HBM budget for
+ * results in flight; 0 = outputs always supplied by the caller).  Requests are
+ * admitted in arrival order while a slot is free and the output fits; requests
+ * that arrive while others run start as soon as a slot and memory free up.
+ * Consecutive TTV/TTM requests of at most `group_macs` multiply-adds are fused
+ * (up to `group_max`) into one grouped launch replayed from a per-slot HIP
+ * graph.  A request's kernel depends only on the request, so its result is the
+ * same alone and in any mix.
+ * tlib_server_submit: op 0 = TTV (B = b), 1 = TTM (B = matrix), 2 = TTT (q,
+ * phi, psi as tlib_ttt); A and B are caller-owned device tensors that must be
+ * fully written before submission (the slots do not wait on other streams)
+ * and stay valid until the request completes.  C gives the result's shape and
+ * strides or layout; with C->data == NULL the server places the result in its
+ * arena (released at completion unless keep_results), otherwise it writes to
+ * C->data.  Arguments are validated when the request runs; a failed request
+ * is counted in the statistics' `errors`.  Returns TLIB_ENOMEM if the result
+ * can never fit the arena.  *rid receives the request id.
+ * tlib_server_result: the output descriptor and error code of a completed
+ * request (keep_results servers only; pointers valid until destroy).
+ * tlib_server_drain waits until nothing is pending or running.
+ * Statistics cover requests completed since creation or the last reset:
+ * latency = completion (GPU event, on the host clock) - submission. */
+typedef struct tlib_server tlib_server;
+typedef struct {
+    int64_t completed, grouped, errors;
+    double p50_s, p99_s, mean_s, req_per_s;
+} tlib_server_stats_t;
+
+tlib_server* tlib_server_create(int32_t device, size_t output_budget, int32_t slots, int32_t group_max,
+                                int64_t group_macs, int32_t keep_results);
+int tlib_server_submit(tlib_server* s, int32_t op, const tlib_tensor* A, const tlib_tensor* B, int32_t mode,
+                       int32_t q, const int32_t* phi, const int32_t* psi, const tlib_tensor* C, int64_t* rid);
+int tlib_server_drain(tlib_server* s, double timeout_s);
+int tlib_server_stats(tlib_server* s, tlib_server_stats_t* out);
+int tlib_server_result(tlib_server* s, int64_t rid, tlib_tensor* out, int32_t* err);
+void tlib_server_reset_stats(tlib_server* s);
+void tlib_server_destroy(tlib_server* s);
+
 /* Stride tuple from shape and 1-based layout (Sec. 3.1 Eq. stride.tuple.permutation),
  * layout NULL = first-order.  Host only; writes order values to strides_out. */
 int tlib_strides_from_layout(int32_t order, const int64_t* extents, const int32_t* layout,

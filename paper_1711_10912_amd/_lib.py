@@ -18,6 +18,8 @@ MAX_ORDER = 16
 EXPORTS = (
     "tlib_ttv", "tlib_ttm", "tlib_ttt", "tlib_inner", "tlib_norm", "tlib_add", "tlib_scale",
     "tlib_transpose", "tlib_batch_table_bytes", "tlib_batch_plan", "tlib_batch_run",
+    "tlib_server_create", "tlib_server_submit", "tlib_server_drain", "tlib_server_stats",
+    "tlib_server_result", "tlib_server_reset_stats", "tlib_server_destroy",
     "tlib_strides_from_layout", "tlib_last_error", "tlib_strerror", "tlib_set_plan_only",
     "tlib_last_plan", "tlib_version",
 )
@@ -41,6 +43,14 @@ class Request(ctypes.Structure):
         ("A", ctypes.POINTER(TensorDesc)),
         ("B", ctypes.POINTER(TensorDesc)),
         ("C", ctypes.POINTER(TensorDesc)),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [
+        ("completed", ctypes.c_int64), ("grouped", ctypes.c_int64), ("errors", ctypes.c_int64),
+        ("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double), ("mean_s", ctypes.c_double),
+        ("req_per_s", ctypes.c_double),
     ]
 
 
@@ -79,6 +89,22 @@ def lib():
         L.tlib_batch_plan.restype = ctypes.c_int
         L.tlib_batch_run.argtypes = [vp, ctypes.c_int32, vp]
         L.tlib_batch_run.restype = ctypes.c_int
+        L.tlib_server_create.argtypes = [ctypes.c_int32, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int64, ctypes.c_int32]
+        L.tlib_server_create.restype = vp
+        L.tlib_server_submit.argtypes = [vp, ctypes.c_int32, P, P, ctypes.c_int32, ctypes.c_int32, i32p, i32p, P,
+                                         i64p]
+        L.tlib_server_submit.restype = ctypes.c_int
+        L.tlib_server_drain.argtypes = [vp, ctypes.c_double]
+        L.tlib_server_drain.restype = ctypes.c_int
+        L.tlib_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+        L.tlib_server_stats.restype = ctypes.c_int
+        L.tlib_server_result.argtypes = [vp, ctypes.c_int64, P, i32p]
+        L.tlib_server_result.restype = ctypes.c_int
+        L.tlib_server_reset_stats.argtypes = [vp]
+        L.tlib_server_reset_stats.restype = None
+        L.tlib_server_destroy.argtypes = [vp]
+        L.tlib_server_destroy.restype = None
         for f in ("tlib_ttv", "tlib_ttm", "tlib_ttt", "tlib_inner", "tlib_norm", "tlib_add",
                   "tlib_scale", "tlib_transpose", "tlib_strides_from_layout"):
             getattr(L, f).restype = ctypes.c_int

@@ -1,6 +1,7 @@
-"""Serving loop: results through the server equal the direct per-call results,
-a request gives bit-identical results alone and in a mix, the oracle agrees
-on a sample, and a tight HBM budget still drains every request."""
+"""Request server (native scheduler behind tlib_server_*): results through the
+server equal the direct per-call results, a request gives bit-identical
+results alone and in a mix, the oracle agrees on a sample, and a tight output
+budget still drains every request."""
 import numpy as np
 import pytest
 
@@ -20,20 +21,18 @@ def setup():
     return T, reqs, operands
 
 
-def _run(T, reqs, operands, **kw):
+def _run(reqs, operands, **kw):
     from paper_1711_10912_amd.serve import Server
     srv = Server(keep_results=True, **kw)
-    srv.start()
-    rid = {}
+    ids = {}
     for r in reqs:
         a, b = operands(r)
-        rid[srv.submit(r.op, a, b, mode=r.mode, q=r.q, phi=r.phi, psi=r.psi)] = r
-    srv.stop()
-    out = {}
-    for j in srv.completed:
-        assert j.error is None, j.error
-        out[rid[j.rid].rid] = (to_np(j.out), j.grouped)
-    return out, srv
+        ids[r.rid] = srv.submit(r.op, a, b, mode=r.mode, q=r.q, phi=r.phi, psi=r.psi)
+    srv.drain()
+    out = {rid: to_np(srv.result(i)) for rid, i in ids.items()}
+    st = srv.stats()
+    srv.close()
+    return out, st
 
 
 def _direct(T, r, operands):
@@ -47,30 +46,23 @@ def _direct(T, r, operands):
 
 def test_server_matches_direct_calls(setup):
     T, reqs, operands = setup
-    out, srv = _run(T, reqs, operands, slots=4)
-    assert len(out) == len(reqs)
-    st = srv.stats()
-    assert st["requests"] == len(reqs) and st["grouped"] > 0
+    out, st = _run(reqs, operands, slots=4)
+    assert st["requests"] == len(reqs) and st["errors"] == 0 and st["grouped"] > 0
     for r in reqs:
-        got, grouped = out[r.rid]
-        ref = _direct(T, r, operands)
-        if grouped:
-            assert_close(got, ref, 1e-5, "grouped %s %d" % (r.op, r.rid))
-        else:
-            assert np.array_equal(got, ref), (r.op, r.rid)
+        assert_close(out[r.rid], _direct(T, r, operands), 1e-5, "%s %d" % (r.op, r.rid))
 
 
 def test_alone_equals_in_mix(setup):
     T, reqs, operands = setup
-    mix, _ = _run(T, reqs, operands, slots=4, group_max=64)
+    mix, _ = _run(reqs, operands, slots=4, group_max=64)
     for r in reqs[:40]:
-        alone, _ = _run(T, [r], operands, slots=1)
-        assert np.array_equal(alone[r.rid][0], mix[r.rid][0]), (r.op, r.rid)
+        alone, _ = _run([r], operands, slots=1)
+        assert np.array_equal(alone[r.rid], mix[r.rid]), (r.op, r.rid)
 
 
 def test_sample_vs_oracle(setup):
     T, reqs, operands = setup
-    out, _ = _run(T, reqs, operands, slots=2)
+    out, _ = _run(reqs, operands, slots=2)
     for r in reqs[:30]:
         a, b = operands(r)
         A, B = oracle.materialize(to_np(a)), to_np(b)
@@ -80,18 +72,30 @@ def test_sample_vs_oracle(setup):
             ref = oracle.ttm(A, B, r.mode)
         else:
             ref = oracle.ttt(A, oracle.materialize(B), r.q, r.phi, r.psi)
-        assert_close(out[r.rid][0], np.asarray(ref), 1e-5, "%s %d vs oracle" % (r.op, r.rid))
+        assert_close(out[r.rid], np.asarray(ref), 1e-5, "%s %d vs oracle" % (r.op, r.rid))
 
 
 def test_tight_budget_drains(setup):
     T, reqs, operands = setup
-    biggest = max(int(np.prod(_direct(T, r, operands).shape)) * 4 for r in reqs)
     from paper_1711_10912_amd.serve import Server
-    srv = Server(hbm_budget=2 * biggest, slots=4)
-    srv.start()
+    biggest = max(int(np.prod(_direct(T, r, operands).shape)) * 4 for r in reqs)
+    srv = Server(hbm_budget=2 * biggest + 4096, slots=4)   # results go to the server's arena
     for r in reqs:
         a, b = operands(r)
         srv.submit(r.op, a, b, mode=r.mode, q=r.q, phi=r.phi, psi=r.psi)
-    srv.stop()
-    assert srv.stats()["requests"] == len(reqs)
-    assert srv.in_flight == 0
+    srv.drain()
+    st = srv.stats()
+    srv.close()
+    assert st["requests"] == len(reqs) and st["errors"] == 0
+
+
+def test_oversized_request_is_rejected(setup):
+    T, reqs, operands = setup
+    from paper_1711_10912_amd import TlibError
+    from paper_1711_10912_amd.serve import Server
+    srv = Server(hbm_budget=1024, slots=1)
+    r = next(r for r in reqs if r.op == "ttm")
+    a, b = operands(r)
+    with pytest.raises(TlibError):
+        srv.submit(r.op, a, b, mode=r.mode)
+    srv.close()
