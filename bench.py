@@ -41,11 +41,12 @@ TTM_M = (16, 64, 256)
 
 
 class Case:
-    __slots__ = ("name", "family", "kernel", "bytes", "flops", "dtype", "fn", "ms")
+    __slots__ = ("name", "family", "kernel", "bytes", "flops", "dtype", "fn", "ms", "planfn")
 
     def __init__(self, name, family, bytes_, flops, dtype, fn):
         self.name, self.family, self.bytes, self.flops, self.dtype, self.fn = name, family, bytes_, flops, dtype, fn
         self.kernel = None
+        self.planfn = None
         self.ms = []
 
     def ideal_s(self):
@@ -61,7 +62,15 @@ def _kernel_label(plan: str) -> str:
         lab += " tile=" + kv["tile"]
     if "vec" in kv:
         lab += " vec=" + kv["vec"]
+    if "mode" in kv:
+        lab += " mode=" + kv["mode"]
     return lab
+
+
+def _plan_later(T, fn, *args, **kw):
+    """The library's plan for a call, taken when the kernel label is needed
+    (after autotuning has settled the choice)."""
+    return lambda: T.plan(fn, *args, **kw)
 
 
 def build_cases(T, torch, dev, quick=False):
@@ -104,7 +113,7 @@ def build_cases(T, torch, dev, quick=False):
                     C = out_view(d, cshape, clay)
                     cases.append(Case("ttv p=%d %s q=%d %s" % (p, lname, q, d), "ttv", s * (N + n + N // n), 2 * N, d,
                                       (lambda A=A, b=b, q=q, C=C: T.ttv(A, b, q, out=C))))
-                    cases[-1].kernel = _kernel_label(T.plan(T.ttv, A, b, q, out=C))
+                    cases[-1].planfn = _plan_later(T, T.ttv, A, b, q, out=C)
                 for q in range(1, p + 1):
                     for m in TTM_M:
                         A = As[(q + m) % 2]
@@ -113,19 +122,19 @@ def build_cases(T, torch, dev, quick=False):
                         nb = s * (N + m * n) + s * (N // n * m)
                         cases.append(Case("ttm p=%d %s q=%d m=%d %s" % (p, lname, q, m, d), "ttm", nb, 2 * N * m, d,
                                           (lambda A=A, B=Bm[m], q=q, C=C: T.ttm(A, B, q, out=C))))
-                        cases[-1].kernel = _kernel_label(T.plan(T.ttm, A, Bm[m], q, out=C))
+                        cases[-1].planfn = _plan_later(T, T.ttm, A, Bm[m], q, out=C)
                 # inner / norm / add on the sweep tensor (FP64 accumulation)
                 res = torch.empty((), dtype=torch.float64, device=dev)
                 cases.append(Case("inner p=%d %s %s" % (p, lname, d), "inner", 2 * s * N, 2 * N, "f64",
                                   (lambda A=As[0], B=As[1], r=res: T.inner(A, B, out=r))))
-                cases[-1].kernel = _kernel_label(T.plan(T.inner, As[0], As[1], out=res))
+                cases[-1].planfn = _plan_later(T, T.inner, As[0], As[1], out=res)
                 cases.append(Case("norm p=%d %s %s" % (p, lname, d), "norm", s * N, 2 * N, "f64",
                                   (lambda A=As[1], r=res: T.norm(A, out=r))))
-                cases[-1].kernel = _kernel_label(T.plan(T.norm, As[1], out=res))
+                cases[-1].planfn = _plan_later(T, T.norm, As[1], out=res)
                 C = out_view(d, shape, lay)
                 cases.append(Case("add p=%d %s %s" % (p, lname, d), "add", 3 * s * N, 2 * N, d,
                                   (lambda A=As[0], B=As[1], C=C: T.add(1.0, A, 1.0, B, out=C))))
-                cases[-1].kernel = _kernel_label(T.plan(T.add, 1.0, As[0], 1.0, As[1], out=C))
+                cases[-1].planfn = _plan_later(T, T.add, 1.0, As[0], 1.0, As[1], out=C)
                 keep.append(res)
 
     # TTT: A (96,80,64,48) x B (64,48,120), A{3,4} <-> B{1,2}
@@ -147,7 +156,7 @@ def build_cases(T, torch, dev, quick=False):
             for c, (A, B, C) in enumerate(sets):
                 cases.append(Case("ttt A=%s %s set=%d" % (lname, d, c), "ttt", nbytes, 2 * Mt * Nt * Kt, d,
                                   (lambda A=A, B=B, C=C: T.ttt(A, B, 2, phi, psi, out=C))))
-                cases[-1].kernel = _kernel_label(T.plan(T.ttt, A, B, 2, phi, psi, out=C))
+                cases[-1].planfn = _plan_later(T, T.ttt, A, B, 2, phi, psi, out=C)
     return cases, keep, outbuf
 
 
@@ -385,6 +394,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--quick", action="store_true", help="p = 3 and 7 only (for profiling runs)")
+    ap.add_argument("--autotune", default="on", choices=("on", "off"),
+                    help="tune the TTM/TTT kernel choice per call shape in the first warmup step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cases-out", default="", help="write per-case timings (JSON lines) here")
     ap.add_argument("--workload", default="sweep", choices=("sweep", "serve"),
@@ -422,9 +433,21 @@ def main():
     cases, keep, outbuf = build_cases(T, torch, dev, quick=args.quick)
     torch.cuda.synchronize()
     print("bench: %d calls per step" % len(cases), file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
+    # Autotuning (kernel choice per call shape) happens in the first warmup
+    # step; the timed steps only use stored choices.
+    tune = "on" if args.autotune == "on" and args.warmup > 0 else "off"
+    T.set_autotune(tune)
+    t_tune = time.perf_counter()
+    for w in range(args.warmup):
         run_step(cases, torch, None)
+        torch.cuda.synchronize()
+        if w == 0:
+            t_tune = time.perf_counter() - t_tune
+            if tune == "on":
+                T.set_autotune("frozen")
     torch.cuda.synchronize()
+    for c in cases:
+        c.kernel = _kernel_label(c.planfn())
 
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in cases]
     step_ms = []
@@ -524,6 +547,8 @@ def main():
                                "A{3,4}<->B{1,2}, 3 A layouts, f32/bf16/f16" + (" [quick: p=3,7 only]" if args.quick else ""),
                    "calls_per_step": len(cases)},
         "roofline_frac_step": round(tot_ideal / (ms_per_step * 1e-3), 4),
+        "autotune": {"mode": tune, "entries": T.autotune_entries(),
+                     "first_warmup_step_s": round(t_tune, 2) if args.warmup > 0 else None},
         "roofline": roof,
         "breakdown": breakdown,
         "kernels": kernels,

@@ -214,6 +214,29 @@ const char* tlib_strerror(int code);
 void tlib_set_plan_only(int enable);
 const char* tlib_last_plan(void);
 
+/* Autotuning of the kernel choice for tlib_ttm and tlib_ttt.  The extents,
+ * layouts and modes of a call decide which kernel and tile shape run fastest
+ * on MI355X; with autotuning the choice is measured instead of taken from the
+ * planner's rules.  Process-wide mode:
+ *   TLIB_AUTOTUNE_OFF     the planner's fixed rules (default);
+ *   TLIB_AUTOTUNE_ON      the first call of each new call shape (op, modes,
+ *                         extents, strides, dtypes) times every applicable
+ *                         candidate on the caller's stream, which makes that
+ *                         one call synchronous, and keeps the fastest; later
+ *                         calls of the shape use the stored choice;
+ *   TLIB_AUTOTUNE_FROZEN  stored choices are used, new shapes get the rules.
+ * Calls on a stream that is capturing a graph never tune.  The table is
+ * shared by all threads and guarded by a lock.  tlib_autotune_entries
+ * returns the number of stored choices; tlib_autotune_clear empties the
+ * table.  Candidates differ only in summation order inside the MFMAs, so
+ * results are reproducible for a fixed table. */
+#define TLIB_AUTOTUNE_OFF 0
+#define TLIB_AUTOTUNE_ON 1
+#define TLIB_AUTOTUNE_FROZEN 2
+int tlib_set_autotune(int mode);  /* returns the previous mode, or -1 (and changes nothing) for an unknown mode */
+int64_t tlib_autotune_entries(void);
+void tlib_autotune_clear(void);
+
 /* Library version string. */
 const char* tlib_version(void);
 

@@ -21,6 +21,7 @@ from ._lib import TlibError
 __all__ = [
     "ttv", "ttm", "ttt", "inner", "norm", "add", "scale", "transpose", "times_tensor",
     "times_vectors", "strides", "layout_of", "empty", "TlibError", "plan", "hopm", "tucker",
+    "set_autotune", "autotune_entries", "autotune_clear",
 ]
 
 _torch = None
@@ -223,6 +224,25 @@ def plan(fn, *args, **kwargs) -> str:
         L.tlib_set_plan_only(0)
         _plan_only = False
     return L.tlib_last_plan().decode()
+
+
+_AUTOTUNE = {"off": 0, "on": 1, "frozen": 2}
+
+
+def set_autotune(mode: str) -> str:
+    """Kernel-choice autotuning for ttm/ttt: "off" (planner rules), "on" (tune
+    each new call shape on its first call, which then synchronises its
+    stream) or "frozen" (use stored choices only).  Returns the previous mode."""
+    prev = _lib.lib().tlib_set_autotune(_AUTOTUNE[mode])
+    return {v: k for k, v in _AUTOTUNE.items()}[prev]
+
+
+def autotune_entries() -> int:
+    return int(_lib.lib().tlib_autotune_entries())
+
+
+def autotune_clear() -> None:
+    _lib.lib().tlib_autotune_clear()
 
 
 from .drivers import hopm, tucker  # noqa: E402

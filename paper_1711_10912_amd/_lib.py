@@ -21,7 +21,7 @@ EXPORTS = (
     "tlib_server_create", "tlib_server_submit", "tlib_server_drain", "tlib_server_stats",
     "tlib_server_result", "tlib_server_reset_stats", "tlib_server_destroy",
     "tlib_strides_from_layout", "tlib_last_error", "tlib_strerror", "tlib_set_plan_only",
-    "tlib_last_plan", "tlib_version",
+    "tlib_last_plan", "tlib_set_autotune", "tlib_autotune_entries", "tlib_autotune_clear", "tlib_version",
 )
 
 
@@ -116,6 +116,12 @@ def lib():
         L.tlib_set_plan_only.restype = None
         L.tlib_last_plan.restype = ctypes.c_char_p
         L.tlib_last_plan.argtypes = []
+        L.tlib_set_autotune.argtypes = [ctypes.c_int]
+        L.tlib_set_autotune.restype = ctypes.c_int
+        L.tlib_autotune_entries.argtypes = []
+        L.tlib_autotune_entries.restype = ctypes.c_int64
+        L.tlib_autotune_clear.argtypes = []
+        L.tlib_autotune_clear.restype = None
         L.tlib_version.restype = ctypes.c_char_p
         L.tlib_version.argtypes = []
         _lib = L

@@ -10,6 +10,7 @@
 // unfolding, no transposed copy), inner/norm and add/scale/transpose as
 // streaming passes.
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -379,11 +380,102 @@ static int run_ttv(const Ten& a, const Ten& b, int mi, const Ten& c, hipStream_t
     return rc ? fail(rc, "ttv: launch failed") : TLIB_OK;
 }
 
+// ------------------------------------------------------------------ autotuning
+//
+// Per-key choice among the launch candidates of one call shape (op, modes,
+// extents, strides and dtypes; data pointers are not part of the key).  With
+// autotuning on, the first call of a new key runs every applicable candidate
+// once to warm up and twice under HIP events on the caller's stream (so that
+// call synchronises the stream), keeps the fastest, and finishes with one
+// more launch of it, which produces the result.  Later calls of the key go
+// straight to the stored pick.  Calls made while the stream is capturing a
+// graph, and calls in plan-only mode, never tune.
+
+constexpr int PICK_NA = -1000;  // the candidate does not apply to this call
+
+static std::atomic<int> g_autotune{0};  // TLIB_AUTOTUNE_OFF / _ON / _FROZEN
+static std::mutex g_tune_mu;
+static std::map<std::string, int> g_tune;
+
+static void key_int(std::string& k, long long v) {
+    char buf[32];
+    snprintf(buf, sizeof(buf), "|%lld", v);
+    k += buf;
+}
+
+static void key_ten(std::string& k, const Ten& t) {
+    char buf[64];
+    snprintf(buf, sizeof(buf), "|%d:%d", t.dtype, t.p);
+    k += buf;
+    for (int r = 0; r < t.p; ++r) {
+        snprintf(buf, sizeof(buf), ",%lld/%lld", (long long)t.n[r], (long long)t.w[r]);
+        k += buf;
+    }
+}
+
+template <class F>
+static int tuned(const std::string& key, const int* cands, int nc, hipStream_t s, F&& run) {
+    const int mode = g_autotune.load();
+    if (mode == TLIB_AUTOTUNE_OFF) return run(-1);
+    int pick = PICK_NA;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) pick = it->second;
+    }
+    if (pick != PICK_NA) {
+        const int rc = run(pick);
+        if (rc != PICK_NA) {
+            g_plan += " autotuned";
+            return rc;
+        }
+        return run(-1);
+    }
+    if (mode != TLIB_AUTOTUNE_ON || g_plan_only) return run(-1);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return run(-1);
+    static thread_local hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!e0 && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) {
+        e0 = e1 = nullptr;
+        return run(-1);
+    }
+    float best = 0.f;
+    int bp = PICK_NA;
+    for (int i = 0; i < nc; ++i) {
+        int rc = run(cands[i]);
+        if (rc == PICK_NA) continue;
+        if (rc != TLIB_OK) return rc;
+        float tmin = 0.f;
+        for (int rep = 0; rep < 2; ++rep) {
+            if (hipEventRecord(e0, s) != hipSuccess) return fail(TLIB_EHIP, "autotune: event record failed");
+            if ((rc = run(cands[i])) != TLIB_OK) return rc;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+                return fail(TLIB_EHIP, "autotune: event wait failed");
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (rep == 0 || ms < tmin) tmin = ms;
+        }
+        if (bp == PICK_NA || tmin < best) {
+            best = tmin;
+            bp = cands[i];
+        }
+    }
+    if (bp == PICK_NA) return run(-1);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = bp;
+    }
+    const int rc = run(bp);
+    if (rc == TLIB_OK) g_plan += " autotuned(new)";
+    return rc;
+}
+
 // ------------------------------------------------------------------ GEMM planning
 
 // dm: M-group dims with strides (X, C); dn: N-group (Y, C); dk: K-group (X, Y).
+// tile_force >= 0 replaces the tile heuristic (autotuning candidates).
 static int run_gemm(int dtype, const void* X, const void* Y, void* C, Dim* dm, int ndm, Dim* dn,
-                    int ndn, Dim* dk, int ndk, const char* op, hipStream_t s) {
+                    int ndn, Dim* dk, int ndk, const char* op, hipStream_t s, int tile_force = -1) {
     // Dims are stored with strides in slots 0/1 as documented above.
     int64_t M = 1, N = 1, K = 1;
     for (int i = 0; i < ndm; ++i) M *= dm[i].n;
@@ -450,6 +542,7 @@ static int run_gemm(int dtype, const void* X, const void* Y, void* C, Dim* dm, i
         else if (N <= 128) tile = wide_acc ? GT_128x64 : GT_128x128;
         else tile = wide_acc ? GT_128x64 : GT_128x128;
         if (ntiles(tile) < 1024 && tile != GT_16x256 && ntiles(GT_64x64) > ntiles(tile)) tile = GT_64x64;
+        if (tile_force >= 0 && tile_force < GT_COUNT) tile = tile_force;
         TileShape ts = tile_shape(tile);
         P.tiles_m = int32_t((M + ts.bm - 1) / ts.bm);
         P.tiles_n = int32_t((N + ts.bn - 1) / ts.bn);
@@ -612,61 +705,113 @@ int tlib_ttv(const tlib_tensor* A, const tlib_tensor* b, int32_t m, const tlib_t
     return run_ttv(a, v, m - 1, c, hipStream_t(stream));
 }
 
-int tlib_ttm(const tlib_tensor* A, const tlib_tensor* B, int32_t m, const tlib_tensor* C,
-             void* stream) {
-    begin_call();
-    Ten a, bm, c;
-    int rc = check_ttm(A, B, m, C, a, bm, c);
-    if (rc) return rc;
-    const int mi = m - 1;
-    // Short contraction: the streaming kernel (B resident in LDS, A streamed).
+// One TTM launch.  pick: TTM_PICK_HEUR (planner's rule), TTM_PICK_STREAM
+// (streaming kernel for this layout), TTM_PICK_ROWS_PLAIN (row kernel with
+// unshifted windows), TTM_PICK_GEMM + tile (tiled GEMM; tile GT_COUNT = the
+// GEMM's own tile rule).  Returns PICK_NA when the pick does not apply.
+enum { TTM_PICK_HEUR = -1, TTM_PICK_STREAM = 0, TTM_PICK_ROWS_PLAIN = 1, TTM_PICK_GEMM = 2 };
+
+static int ttm_dispatch(const Ten& a, const Ten& bm, int mi, const Ten& c, int pick, void* stream) {
+    // Short contraction: the streaming kernels (B resident in LDS, A streamed).
     {
         const int64_t Mr = bm.n[0], Kr = a.n[mi];
-        const int ks = ttm_stream_ks(a.dtype, int(std::min<int64_t>(Kr, 1 << 20)));
-        const int fm = Mr <= 16 ? 1 : Mr <= 64 ? 4 : Mr <= 256 ? 16 : 0;
         Dim dn[MAXP];
         int ndn = 0;
         for (int r = 0; r < a.p; ++r)
             if (r != mi) dn[ndn++] = {a.n[r], {a.w[r], c.w[r], 0}};
-        ndn = coalesce(dn, ndn, 2, 1);
-        TtmParams T{};
-        const bool wide = a.dtype == TLIB_BF16 || a.dtype == TLIB_F16;
-        const int kstep = wide ? 32 : 4;
-        const int64_t m16 = int64_t(fm) * 16, kp = int64_t(ks) * kstep;
-        const int64_t lds = wide ? m16 * (kp + 8) * 2 : kp * (m16 + (a.dtype == TLIB_F64 ? 4 : 16)) * esize(a.dtype);
-        int64_t cmin = INT64_MAX;
-        for (int i = 0; i < ndn; ++i) cmin = std::min(cmin, dn[i].s[1]);
+        ndn = coalesce(dn, ndn, 2, 1);  // C's innermost column dim first
+        int64_t cmin = INT64_MAX, ncols = 1;
+        for (int i = 0; i < ndn; ++i) {
+            cmin = std::min(cmin, dn[i].s[1]);
+            ncols *= dn[i].n;
+        }
         const bool trans = Mr > 1 && c.w[mi] < cmin;
-        // Measured on MI355X over the order-p sweep: the streaming kernel wins
-        // whenever C is contiguous along j, for longer contractions, and for
-        // FP64 from k = 16; with k < 16, C strided along j and many rows the
-        // tiled GEMM's larger column runs win.
-        const bool prefer = trans || Kr >= 32 || (Kr >= 16 && a.dtype == TLIB_F64) ||
-                            (Mr <= 16 && a.dtype != TLIB_F64);
-        if (prefer && ks > 0 && fm > 0 && Kr <= 64 && lds <= 65536 && fill_grp(T.gn, dn, ndn, 0, 1)) {
-            T.X = bm.data;
-            T.Y = a.data;
-            T.C = c.data;
-            T.M = int32_t(Mr);
-            T.N = int32_t(T.gn.total);
-            T.K = int32_t(Kr);
-            T.sXm = bm.w[0];
-            T.sXk = bm.w[1];
-            T.sYk = a.w[mi];
-            T.sCm = c.w[mi];
-            const int64_t cols = fm >= 16 ? 64 : fm >= 4 ? 128 : 256;  // columns per workgroup tile
-            const int64_t tiles = (T.N + cols - 1) / cols;
-            const int per_cu = lds <= 20480 ? 4 : lds <= 40960 ? 3 : 2;
-            const int grid = int(std::max<int64_t>(1, std::min<int64_t>(tiles, 256 * per_cu)));
-            plan_note("ttm stream dtype=%s M=%lld N=%d K=%lld dims=%d fm=%d cols=%lld ks=%d trans=%d lds=%lld grid=%d "
-                      "tiles=%lld",
-                      dname(a.dtype), (long long)Mr, T.N, (long long)Kr, ndn, fm, (long long)cols, ks, trans ? 1 : 0,
-                      (long long)lds, grid, (long long)tiles);
-            if (g_plan_only) return TLIB_OK;
-            int rc2 = launch_ttm_stream(a.dtype, T, fm, ks, trans, grid, hipStream_t(stream));
-            return rc2 ? fail(rc2, "ttm: launch failed") : TLIB_OK;
+        const bool wide = a.dtype == TLIB_BF16 || a.dtype == TLIB_F16;
+        if (trans && pick <= 0) {
+            // C contiguous along j
+            const int ks = ttm_stream_ks(a.dtype, int(std::min<int64_t>(Kr, 1 << 20)));
+            const int fm = Mr <= 16 ? 1 : Mr <= 64 ? 4 : Mr <= 256 ? 16 : 0;
+            TtmParams T{};
+            const int kstep = wide ? 32 : 4;
+            const int64_t m16 = int64_t(fm) * 16, kp = int64_t(ks) * kstep;
+            const int64_t lds =
+                wide ? m16 * (kp + 8) * 2 : kp * (m16 + (a.dtype == TLIB_F64 ? 4 : 16)) * esize(a.dtype);
+            if (ks > 0 && fm > 0 && Kr <= 64 && lds <= 65536 && fill_grp(T.gn, dn, ndn, 0, 1)) {
+                T.X = bm.data;
+                T.Y = a.data;
+                T.C = c.data;
+                T.M = int32_t(Mr);
+                T.N = int32_t(T.gn.total);
+                T.K = int32_t(Kr);
+                T.sXm = bm.w[0];
+                T.sXk = bm.w[1];
+                T.sYk = a.w[mi];
+                T.sCm = c.w[mi];
+                const int fn = fm >= 16 ? 1 : fm >= 4 ? 2 : 4;
+                const int64_t cols = 64 * fn;  // columns per workgroup tile
+                const int64_t tiles = (T.N + cols - 1) / cols;
+                const int per_cu = lds <= 20480 ? 4 : lds <= 40960 ? 3 : 2;
+                const int grid = int(std::max<int64_t>(1, std::min<int64_t>(tiles, 256 * per_cu)));
+                plan_note("ttm stream dtype=%s M=%lld N=%d K=%lld dims=%d fm=%d cols=%lld ks=%d lds=%lld grid=%d "
+                          "tiles=%lld",
+                          dname(a.dtype), (long long)Mr, T.N, (long long)Kr, ndn, fm, (long long)cols, ks,
+                          (long long)lds, grid, (long long)tiles);
+                if (g_plan_only) return TLIB_OK;
+                int rc2 = launch_ttm_stream(a.dtype, T, fm, ks, true, grid, hipStream_t(stream));
+                return rc2 ? fail(rc2, "ttm: launch failed") : TLIB_OK;
+            }
+        } else if (!trans && pick <= 1 && Mr <= 256 && ndn >= 1 && ndn <= GMAXD + 1 && ncols < (int64_t(1) << 31)) {
+            // C strided along j: runs along C's innermost column dim
+            TtmRowParams R{};
+            const int64_t n_lo = dn[0].n, sclo = dn[0].s[1];
+            const int lpc = 128 / esize(acc_dtype(a.dtype));  // C elements per 128-byte line
+            int mode = TTM_ROWS_PLAIN;
+            if (sclo == 1 && c.w[mi] == n_lo && n_lo <= 32) mode = n_lo <= 16 ? TTM_ROWS_BAND1 : TTM_ROWS_BAND;
+            else if (sclo == 1 && ttm_rows_ks(a.dtype, TTM_ROWS_ALIGNED, int(std::min<int64_t>(Kr, 1 << 20))) > 0)
+                mode = TTM_ROWS_ALIGNED;
+            if (pick == TTM_PICK_ROWS_PLAIN) {
+                if (mode == TTM_ROWS_PLAIN) return PICK_NA;  // same launch as the streaming pick
+                mode = TTM_ROWS_PLAIN;
+            }
+            const int ks = ttm_rows_ks(a.dtype, mode, int(std::min<int64_t>(Kr, 1 << 20)));
+            const int64_t lds = ks > 0 ? ttm_rows_lds(a.dtype, mode, int(Mr), ks) : INT64_MAX;
+            const int64_t tc = mode == TTM_ROWS_ALIGNED ? (n_lo + lpc - 1 + 63) / 64
+                               : mode == TTM_ROWS_PLAIN ? (n_lo + 63) / 64
+                                                        : 1;
+            const int64_t units = ncols / n_lo * tc;
+            if (ks > 0 && lds <= 65536 && units < (int64_t(1) << 31) && fill_grp(R.gh, dn + 1, ndn - 1, 0, 1)) {
+                R.X = bm.data;
+                R.Y = a.data;
+                R.C = c.data;
+                R.M = int32_t(Mr);
+                R.K = int32_t(Kr);
+                R.sXm = bm.w[0];
+                R.sXk = bm.w[1];
+                R.sYk = a.w[mi];
+                R.sCm = c.w[mi];
+                R.n_lo = int32_t(n_lo);
+                R.Tc = int32_t(tc);
+                R.sYlo = dn[0].s[0];
+                R.sClo = sclo;
+                R.units = units;
+                R.fd_tc = make_fastdiv(uint32_t(tc));
+                R.fd_lo = make_fastdiv(uint32_t(n_lo));
+                const int per_cu = int(std::max<int64_t>(1, std::min<int64_t>(4, 160 * 1024 / lds)));
+                const int grid = int(std::max<int64_t>(1, std::min<int64_t>((units + 3) / 4, 256 * per_cu)));
+                plan_note("ttm rows dtype=%s mode=%s M=%lld K=%lld n_lo=%lld runs=%lld chunks=%lld ks=%d lds=%lld "
+                          "grid=%d",
+                          dname(a.dtype),
+                          mode == TTM_ROWS_BAND ? "band" : mode == TTM_ROWS_BAND1 ? "band1"
+                                                 : mode == TTM_ROWS_ALIGNED ? "aligned" : "plain",
+                          (long long)Mr, (long long)Kr, (long long)n_lo, (long long)(ncols / n_lo), (long long)tc, ks,
+                          (long long)lds, grid);
+                if (g_plan_only) return TLIB_OK;
+                int rc2 = launch_ttm_rows(a.dtype, R, mode, ks, grid, hipStream_t(stream));
+                return rc2 ? fail(rc2, "ttm: launch failed") : TLIB_OK;
+            }
         }
     }
+    if (pick == TTM_PICK_STREAM || pick == TTM_PICK_ROWS_PLAIN) return PICK_NA;
     // GEMM roles: X = B (M = j), Y = A (N = the modes of A other than m), K = mode m.
     Dim dm[1] = {{bm.n[0], {bm.w[0], c.w[mi], 0}}};
     Dim dn[MAXP];
@@ -674,7 +819,43 @@ int tlib_ttm(const tlib_tensor* A, const tlib_tensor* B, int32_t m, const tlib_t
     for (int r = 0; r < a.p; ++r)
         if (r != mi) dn[ndn++] = {a.n[r], {a.w[r], c.w[r], 0}};
     Dim dk[1] = {{a.n[mi], {bm.w[1], a.w[mi], 0}}};
-    return run_gemm(a.dtype, bm.data, a.data, c.data, dm, 1, dn, ndn, dk, 1, "ttm", hipStream_t(stream));
+    const int tile = pick >= TTM_PICK_GEMM ? pick - TTM_PICK_GEMM : -1;
+    return run_gemm(a.dtype, bm.data, a.data, c.data, dm, 1, dn, ndn, dk, 1, "ttm", hipStream_t(stream),
+                    tile < GT_COUNT ? tile : -1);
+}
+
+int tlib_set_autotune(int mode) {
+    if (mode != TLIB_AUTOTUNE_OFF && mode != TLIB_AUTOTUNE_ON && mode != TLIB_AUTOTUNE_FROZEN) return -1;
+    return g_autotune.exchange(mode);
+}
+
+int64_t tlib_autotune_entries(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return int64_t(g_tune.size());
+}
+
+void tlib_autotune_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+}
+
+int tlib_ttm(const tlib_tensor* A, const tlib_tensor* B, int32_t m, const tlib_tensor* C,
+             void* stream) {
+    begin_call();
+    Ten a, bm, c;
+    int rc = check_ttm(A, B, m, C, a, bm, c);
+    if (rc) return rc;
+    const int mi = m - 1;
+    static const int cands[] = {TTM_PICK_STREAM,          TTM_PICK_ROWS_PLAIN,        TTM_PICK_GEMM + GT_COUNT,
+                                TTM_PICK_GEMM + GT_128x64, TTM_PICK_GEMM + GT_128x128, TTM_PICK_GEMM + GT_64x128,
+                                TTM_PICK_GEMM + GT_256x64};
+    std::string key = "ttm";
+    key_int(key, m);
+    key_ten(key, a);
+    key_ten(key, bm);
+    key_ten(key, c);
+    return tuned(key, cands, int(sizeof(cands) / sizeof(cands[0])), hipStream_t(stream),
+                 [&](int pick) { return ttm_dispatch(a, bm, mi, c, pick, stream); });
 }
 
 int tlib_ttt(const tlib_tensor* A, const tlib_tensor* B, int32_t q, const int32_t* phi,
@@ -704,11 +885,23 @@ int tlib_ttt(const tlib_tensor* A, const tlib_tensor* B, int32_t q, const int32_
     if ((rc = check_output(c, "C"))) return rc;
     if (overlaps(c, a) || overlaps(c, b)) return fail(TLIB_EALIAS, "ttt: C overlaps an input");
     // GEMM roles: X = A (M = free A modes), Y = B (N = free B modes), K = pairs.
-    Dim dm[MAXP], dn[MAXP], dk[MAXP];
-    for (int k = 0; k < r; ++k) dm[k] = {a.n[phi[k] - 1], {a.w[phi[k] - 1], c.w[k], 0}};
-    for (int k = 0; k < s; ++k) dn[k] = {b.n[psi[k] - 1], {b.w[psi[k] - 1], c.w[r + k], 0}};
-    for (int k = 0; k < q; ++k) dk[k] = {a.n[phi[r + k] - 1], {a.w[phi[r + k] - 1], b.w[psi[s + k] - 1], 0}};
-    return run_gemm(a.dtype, a.data, b.data, c.data, dm, r, dn, s, dk, q, "ttt", hipStream_t(stream));
+    auto run = [&](int tile) {
+        Dim dm[MAXP], dn[MAXP], dk[MAXP];
+        for (int k = 0; k < r; ++k) dm[k] = {a.n[phi[k] - 1], {a.w[phi[k] - 1], c.w[k], 0}};
+        for (int k = 0; k < s; ++k) dn[k] = {b.n[psi[k] - 1], {b.w[psi[k] - 1], c.w[r + k], 0}};
+        for (int k = 0; k < q; ++k)
+            dk[k] = {a.n[phi[r + k] - 1], {a.w[phi[r + k] - 1], b.w[psi[s + k] - 1], 0}};
+        return run_gemm(a.dtype, a.data, b.data, c.data, dm, r, dn, s, dk, q, "ttt", hipStream_t(stream), tile);
+    };
+    static const int cands[] = {GT_16x256, GT_64x128, GT_128x128, GT_256x64, GT_64x64, GT_128x64, GT_256x32};
+    std::string key = "ttt";
+    key_int(key, q);
+    for (int k = 0; k < a.p; ++k) key_int(key, phi[k]);
+    for (int k = 0; k < b.p; ++k) key_int(key, psi[k]);
+    key_ten(key, a);
+    key_ten(key, b);
+    key_ten(key, c);
+    return tuned(key, cands, int(sizeof(cands) / sizeof(cands[0])), hipStream_t(stream), run);
 }
 
 static int run_dot(const Ten& a, const Ten* b, double* out, bool sq, hipStream_t s, const char* op) {

@@ -106,6 +106,31 @@ struct TtmParams {
     Grp gn;  // s0 = Y stride, s1 = C stride
 };
 
+// Streaming TTM with C strided along j (the row index of B): the columns nu
+// split into runs of n_lo along C's innermost column dim (strides sYlo in A,
+// sClo in C) and the remaining column dims gh (s0 = A stride, s1 = C stride).
+// Work units are (run h, chunk t) pairs; mode selects how rows are written:
+//   TTM_ROWS_PLAIN   64-column windows starting at 64 t
+//   TTM_ROWS_ALIGNED 64-column windows shifted per row to start on a 128-byte
+//                    line of C (needs sClo == 1; computes 128 bytes more)
+//   TTM_ROWS_BAND    whole runs, with rows j contiguous in C (sClo == 1,
+//                    sCm == n_lo): written as one linear range per row group
+//                    (two column blocks, n_lo <= 32; BAND1: one, n_lo <= 16)
+enum { TTM_ROWS_PLAIN = 0, TTM_ROWS_ALIGNED = 1, TTM_ROWS_BAND = 2, TTM_ROWS_BAND1 = 3 };
+struct TtmRowParams {
+    const void* X;
+    const void* Y;
+    void* C;
+    int32_t M, K;
+    int64_t sXm, sXk, sYk, sCm;
+    int32_t n_lo;
+    int32_t Tc;  // chunks per run
+    int64_t sYlo, sClo;
+    int64_t units;  // runs * Tc
+    FastDiv fd_tc, fd_lo;
+    Grp gh;
+};
+
 // Work table of a grouped launch (k_batch.hip): a header followed by items.
 struct BatchHeader {
     int32_t n_items;
@@ -144,6 +169,10 @@ int launch_gemm(int dtype, int tile, const GemmParams& p, hipStream_t s);
 // fm: row blocks (1, 4 or 16); ks: k-steps from ttm_stream_ks (0 = unsupported)
 int launch_ttm_stream(int dtype, const TtmParams& p, int fm, int ks, bool trans, int grid, hipStream_t s);
 int ttm_stream_ks(int dtype, int k);
+// Row-streaming TTM (TtmRowParams); ks from ttm_rows_ks, lds from ttm_rows_lds.
+int launch_ttm_rows(int dtype, const TtmRowParams& p, int mode, int ks, int grid, hipStream_t s);
+int ttm_rows_ks(int dtype, int mode, int k);
+int64_t ttm_rows_lds(int dtype, int mode, int m, int ks);
 int launch_gemm_generic(int dtype, const void* X, const void* Y, void* C, const GDims& m,
                         const GDims& n, const GDims& k, hipStream_t s);
 

@@ -1,16 +1,18 @@
 // Streaming TTM (Sec. 5.2 Eq. ttm) for a short contraction (n_m <= 64):
 //   C(.., j, ..) = sum_k B(j, k) A(.., k, ..)
-// With a short k the cost is writing C (m/n_m times the size of A), so the
-// kernel is built around keeping stores flowing:
+// With a short k the cost is writing C (m/n_m times the size of A), so both
+// kernels here are built around the stores:
 //   * each persistent workgroup stages the whole matrix B (m x n_m, zero-padded
-//     to the MFMA k-step) in LDS once;
-//   * it then walks column tiles of A (the columns nu are A's modes other than
-//     m, decoded through up to four (extent, stride) pairs); each wave loads
-//     its A fragments straight from global memory into MFMA operand registers,
-//     issuing the loads of its next tile before the MFMAs and stores of the
-//     current one;
-//   * the MFMA operand order is chosen so that the lanes of a store run along
-//     C's unit-stride dimension.
+//     to the MFMA k-step) in LDS once and then walks a contiguous range of
+//     units of A's columns nu (the modes other than m), loading A fragments
+//     straight into MFMA operand registers one unit ahead;
+//   * ttm_stream_kernel serves C contiguous along j: MFMA operands are swapped
+//     so the lanes of a result register run along j;
+//   * ttm_rows_kernel serves C strided along j: results go through a small
+//     per-wave LDS stage and leave as row windows that start on 128-byte lines
+//     (or as one linear range when rows of a run are adjacent in C), because
+//     stores that split lines between instructions cost up to half the
+//     write bandwidth on MI355X.
 // MFMAs: v_mfma_f64_16x16x4 (FP64), v_mfma_f32_16x16x4 (FP32) and
 // v_mfma_f32_16x16x32_{bf16,f16} (16-bit inputs, FP32 accumulation).
 #include <algorithm>
@@ -57,11 +59,58 @@ __device__ __forceinline__ typename SMfma<TI>::acc_t smfma(typename SMfma<TI>::f
 __device__ __forceinline__ uint32_t raw16(const bf16_t* p) { return *reinterpret_cast<const uint16_t*>(p); }
 __device__ __forceinline__ uint32_t raw16(const f16_t* p) { return *reinterpret_cast<const uint16_t*>(p); }
 
-// Per wave FM row blocks and FN column blocks of 16; WGM of the four waves
-// split the rows (WGM * FM * 16 >= M), the others split the columns; KS
-// k-steps.  TRANS: MFMA operands swapped so the lanes of the result run
-// along M.
-template <typename TI, int FM, int FN, int KS, bool TRANS, int WGM>
+// The MFMA A-operand fragments of one column (base y) for KS k-steps: lane
+// (rl, kq) supplies k = s*KSTEP + kq (FP32/FP64) or k = s*32 + 8*kq + e, e < 8
+// (16-bit, packed in pairs).  Loads are unconditional from clamped in-range
+// addresses (k < K, and the caller clamps the column); out-of-range entries
+// are replaced by zero afterwards, so no load sits behind a branch.
+template <typename TI, int KS>
+__device__ __forceinline__ void load_frags(const TI* y, int64_t sk, int K, bool cv,
+                                           int kq, typename SMfma<TI>::frag_t (&f)[KS]) {
+    constexpr int KSTEP = SMfma<TI>::KSTEP;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        if constexpr (sizeof(TI) == 2) {
+            uint32_t w[4];
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const int k0 = s * 32 + 8 * kq + 2 * h;
+                const uint32_t lo = raw16(y + int64_t(min(k0, K - 1)) * sk);
+                const uint32_t hi = raw16(y + int64_t(min(k0 + 1, K - 1)) * sk);
+                w[h] = (cv && k0 < K ? lo : 0u) | ((cv && k0 + 1 < K ? hi : 0u) << 16);
+            }
+            f[s] = u4s_t{w[0], w[1], w[2], w[3]};
+        } else {
+            const int k = s * KSTEP + kq;
+            const TI v = y[int64_t(min(k, K - 1)) * sk];
+            f[s] = (cv && k < K) ? v : TI(0);
+        }
+    }
+}
+
+// Persistent work walk shared by the streaming TTM kernels.  Workgroups are
+// dealt round-robin to the eight XCDs, so the grid is split into min(8, G)
+// groups by blockIdx % 8 and each group walks its own contiguous range of
+// units: neighbouring units, which share cache lines of C at their edges, are
+// written through the same L2.  `workers` units are in flight per workgroup.
+struct Walk {
+    int64_t u, end, step;
+};
+__device__ __forceinline__ Walk xcd_walk(int64_t units, int workers, int worker) {
+    const int G = gridDim.x, ng = G < 8 ? G : 8, xg = blockIdx.x % ng, ix = blockIdx.x / ng;
+    const int nx = (G - xg + ng - 1) / ng;
+    Walk w;
+    w.end = int64_t(xg + 1) * units / ng;
+    w.u = int64_t(xg) * units / ng + int64_t(ix) * workers + worker;
+    w.step = int64_t(nx) * workers;
+    return w;
+}
+
+// C contiguous along j (TRANS): each wave owns FM row blocks (all rows) of a
+// 16*FN-column strip; the MFMA operands are swapped so that the lanes of a
+// result register run along j, and every store instruction writes four
+// columns' 16-row segments.
+template <typename TI, int FM, int FN, int KS>
 __global__ __launch_bounds__(256) void ttm_stream_kernel(TtmParams P) {
     using TA = typename AccOf<TI>::type;
     using acc_t = typename SMfma<TI>::acc_t;
@@ -69,21 +118,20 @@ __global__ __launch_bounds__(256) void ttm_stream_kernel(TtmParams P) {
     constexpr bool WIDE = sizeof(TI) == 2;
     constexpr int KSTEP = SMfma<TI>::KSTEP;
     constexpr int KP = KS * KSTEP;             // padded contraction length
-    constexpr int M16 = WGM * FM * 16;
+    constexpr int M16 = FM * 16;
     constexpr int PB = WIDE ? (KP + 8) : (M16 + (sizeof(TI) == 8 ? 4 : 16));
     constexpr int RQ = std::is_same<TI, double>::value ? 1 : 4;  // result row of (kq, r): RQ*kq + RR*r
     constexpr int RR = std::is_same<TI, double>::value ? 4 : 1;
-    constexpr int WGN = 4 / WGM;
-    constexpr int COLS = WGN * FN * 16;        // columns per workgroup tile
+    constexpr int COLS = 4 * FN * 16;          // columns per workgroup tile
 
     extern __shared__ __align__(16) unsigned char smem[];
     using RT = typename std::conditional<WIDE, uint16_t, TI>::type;
     RT* Bs = reinterpret_cast<RT*>(smem);
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // wave index through readfirstlane, so that everything derived from it
+    // (unit, run, chunk, block activity) is known to be wave-uniform
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int rl = lane & 15, kq = lane >> 4;
-    const int wm = wave % WGM, wn = wave / WGM;
-    const int row0 = wm * FM * 16;
     const TI* X = (const TI*)P.X;
     const TI* Y = (const TI*)P.Y;
     TA* C = (TA*)P.C;
@@ -104,43 +152,27 @@ __global__ __launch_bounds__(256) void ttm_stream_kernel(TtmParams P) {
     }
     __syncthreads();
 
-    const int T = (P.N + COLS - 1) / COLS;
+    const int64_t T = (int64_t(P.N) + COLS - 1) / COLS;
     frag_t ycur[FN][KS], ynxt[FN][KS];
 
     // A fragments of tile t for this wave: block j holds columns
     // t*COLS + (wave*FN + j)*16 + rl; lane (rl, kq) supplies k = s*KSTEP + kq
     // (FP32/FP64) or k = s*32 + 8*kq + e (16-bit).
-    auto load_y = [&](int t, frag_t (&y)[FN][KS]) {
+    auto load_y = [&](int64_t t, frag_t (&y)[FN][KS]) {
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
-            const int col = t * COLS + (wn * FN + j) * 16 + rl;
+            const int col = int(t * COLS) + (wave * FN + j) * 16 + rl;
             const bool cv = col < P.N;
-            const int64_t yo = cv ? grp_off0(uint32_t(col), P.gn) : 0;
-#pragma unroll
-            for (int s = 0; s < KS; ++s) {
-                if constexpr (WIDE) {
-                    uint32_t w[4];
-#pragma unroll
-                    for (int h = 0; h < 4; ++h) {
-                        const int k0 = s * 32 + 8 * kq + 2 * h;
-                        const uint32_t lo = (cv && k0 < P.K) ? raw16(Y + yo + int64_t(k0) * P.sYk) : 0u;
-                        const uint32_t hi = (cv && k0 + 1 < P.K) ? raw16(Y + yo + int64_t(k0 + 1) * P.sYk) : 0u;
-                        w[h] = lo | (hi << 16);
-                    }
-                    y[j][s] = u4s_t{w[0], w[1], w[2], w[3]};
-                } else {
-                    const int k = s * KSTEP + kq;
-                    y[j][s] = (cv && k < P.K) ? Y[yo + int64_t(k) * P.sYk] : TI(0);
-                }
-            }
+            const int64_t yo = grp_off0(uint32_t(cv ? col : P.N - 1), P.gn);
+            load_frags<TI, KS>(Y + yo, P.sYk, P.K, cv, kq, y[j]);
         }
     };
 
-    int t = blockIdx.x;
-    if (t < T) load_y(t, ycur);
-    for (; t < T; t += gridDim.x) {
-        const int tn = t + gridDim.x;
-        if (tn < T) load_y(tn, ynxt);
+    Walk wk = xcd_walk(T, 1, 0);
+    if (wk.u < wk.end) load_y(wk.u, ycur);
+    for (; wk.u < wk.end; wk.u += wk.step) {
+        const int64_t tn = wk.u + wk.step;
+        if (tn < wk.end) load_y(tn, ynxt);
 
         acc_t acc[FM][FN];
 #pragma unroll
@@ -152,48 +184,26 @@ __global__ __launch_bounds__(256) void ttm_stream_kernel(TtmParams P) {
 #pragma unroll
             for (int i = 0; i < FM; ++i) {
                 frag_t b;
-                if constexpr (WIDE) b = *reinterpret_cast<const u4s_t*>(&Bs[(row0 + i * 16 + rl) * PB + s * 32 + 8 * kq]);
-                else b = Bs[(s * KSTEP + kq) * PB + row0 + i * 16 + rl];
+                if constexpr (WIDE) b = *reinterpret_cast<const u4s_t*>(&Bs[(i * 16 + rl) * PB + s * 32 + 8 * kq]);
+                else b = Bs[(s * KSTEP + kq) * PB + i * 16 + rl];
 #pragma unroll
-                for (int j = 0; j < FN; ++j) {
-                    if constexpr (TRANS) acc[i][j] = smfma<TI>(ycur[j][s], b, acc[i][j]);
-                    else acc[i][j] = smfma<TI>(b, ycur[j][s], acc[i][j]);
-                }
+                for (int j = 0; j < FN; ++j) acc[i][j] = smfma<TI>(ycur[j][s], b, acc[i][j]);
             }
         }
 
-        // stores: block (i, j) covers rows (M) 16i.. and columns t*COLS + (wave*FN+j)*16 ..
+        // lane column = row of M (rl), registers = columns nu
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
-            const int cbase = t * COLS + (wn * FN + j) * 16;
-            if constexpr (!TRANS) {
-                // lane column = nu (rl), registers = rows of M
-                // the row part of each address is uniform across the wave
-                // except for kq: one lane base plus scalar offsets
-                const int col = cbase + rl;
+            const int cbase = int(wk.u * COLS) + (wave * FN + j) * 16;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int col = cbase + RQ * kq + RR * r;
                 if (col < P.N) {
-                    TA* cp = C + grp_off1(uint32_t(col), P.gn) + int64_t(row0 + RQ * kq) * P.sCm;
-                    const int rmax = P.M - row0 - RQ * kq;
+                    TA* cp = C + grp_off1(uint32_t(col), P.gn) + int64_t(rl) * P.sCm;
+                    const int rmax = P.M - rl;
 #pragma unroll
                     for (int i = 0; i < FM; ++i)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int dr = i * 16 + RR * r;
-                            if (dr < rmax) cp[int64_t(dr) * P.sCm] = acc[i][j][r];
-                        }
-                }
-            } else {
-                // lane column = row of M (rl), registers = columns nu
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int col = cbase + RQ * kq + RR * r;
-                    if (col < P.N) {
-                        TA* cp = C + grp_off1(uint32_t(col), P.gn) + int64_t(row0 + rl) * P.sCm;
-                        const int rmax = P.M - row0 - rl;
-#pragma unroll
-                        for (int i = 0; i < FM; ++i)
-                            if (i * 16 < rmax) cp[int64_t(i * 16) * P.sCm] = acc[i][j][r];
-                    }
+                        if (i * 16 < rmax) cp[int64_t(i * 16) * P.sCm] = acc[i][j][r];
                 }
             }
         }
@@ -204,34 +214,175 @@ __global__ __launch_bounds__(256) void ttm_stream_kernel(TtmParams P) {
     }
 }
 
+// Row-streaming TTM for C strided along j (see TtmRowParams).  B (M x K,
+// zero-padded to 16-row blocks and the MFMA k-step) is staged in LDS once per
+// workgroup; each of the four waves then walks its own (run, chunk) units: it
+// loads the chunk's A fragments (16*FN columns, all k) into registers, issuing
+// the loads of its next unit first, and for every 16-row block of C runs the
+// MFMAs, stages the block in its own LDS rows and writes them back as whole
+// 64-column windows (or, in band mode, as one linear range).
+template <typename TI, int FN, int KS, int MODE>
+__global__ __launch_bounds__(256) void ttm_rows_kernel(TtmRowParams P) {
+    using TA = typename AccOf<TI>::type;
+    using acc_t = typename SMfma<TI>::acc_t;
+    using frag_t = typename SMfma<TI>::frag_t;
+    constexpr bool WIDE = sizeof(TI) == 2;
+    constexpr bool F64 = std::is_same<TI, double>::value;
+    constexpr int KSTEP = SMfma<TI>::KSTEP;
+    constexpr int KP = KS * KSTEP;
+    constexpr int RQ = F64 ? 1 : 4;  // result row of (kq, r): RQ*kq + RR*r
+    constexpr int RR = F64 ? 4 : 1;
+    constexpr int W = 64;                       // written columns per row window
+    constexpr int L = 128 / int(sizeof(TA));    // elements of C per 128-byte line
+    constexpr int SR = F64 ? 4 : 16;            // rows staged per pass (one result register for FP64)
+    constexpr int SP = FN * 16 + 2;              // FP64 staging: row pitch
+    constexpr int SPC = 20;                      // FP32 staging: column pitch (16-byte aligned)
+    constexpr int STG = F64 ? SR * SP : FN * 16 * SPC;  // staged elements per wave
+    using RT = typename std::conditional<WIDE, uint16_t, TI>::type;
+    static_assert(MODE != TTM_ROWS_ALIGNED || FN * 16 >= W + L, "aligned windows need W + L staged columns");
+    static_assert(MODE != TTM_ROWS_PLAIN || FN * 16 >= W, "plain windows need W staged columns");
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    // wave index through readfirstlane, so that everything derived from it
+    // (unit, run, chunk, block activity) is known to be wave-uniform
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int rl = lane & 15, kq = lane >> 4;
+    const int M16 = (P.M + 15) & ~15;
+    const int PB = WIDE ? (KP + 8) : (M16 + (F64 ? 4 : 16));
+    RT* Bs = reinterpret_cast<RT*>(smem);
+    const int bbytes = ((WIDE ? M16 * PB : KP * PB) * int(sizeof(RT)) + 15) & ~15;
+    TA* stg = reinterpret_cast<TA*>(smem + bbytes) + wave * STG;
+    auto stage_at = [&](int row, int col) -> TA { return F64 ? stg[row * SP + col] : stg[col * SPC + row]; };
+    const TI* X = (const TI*)P.X;
+    const TI* Y = (const TI*)P.Y;
+    TA* C = (TA*)P.C;
+
+    for (int e = tid; e < M16 * KP; e += 256) {
+        int m, k;
+        if constexpr (WIDE) { m = e / KP; k = e - m * KP; }
+        else { k = e / M16; m = e - k * M16; }
+        RT v = RT(0);
+        if (m < P.M && k < P.K) {
+            const TI* src = X + int64_t(m) * P.sXm + int64_t(k) * P.sXk;
+            if constexpr (WIDE) v = uint16_t(raw16(src));
+            else v = *src;
+        }
+        if constexpr (WIDE) Bs[m * PB + k] = v;
+        else Bs[k * PB + m] = v;
+    }
+    __syncthreads();
+
+    // unit u -> run h (A and C offsets of its first element), chunk t and the
+    // first staged column c0
+    auto unit_pos = [&](int64_t u, int64_t& ya, int64_t& yc, int& t, int& c0) {
+        const uint32_t uu = uint32_t(u);
+        const uint32_t h = fdiv(uu, P.fd_tc);
+        t = int(uu - h * uint32_t(P.Tc));
+        grp_decode(h, P.gh, ya, yc);
+        c0 = MODE == TTM_ROWS_ALIGNED ? W * t - L : MODE == TTM_ROWS_PLAIN ? W * t : 0;
+    };
+    frag_t ycur[FN][KS];
+    auto load_y = [&](int64_t u, frag_t (&y)[FN][KS]) {
+        int64_t ya, yc;
+        int t, c0;
+        unit_pos(u, ya, yc, t, c0);
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int col = c0 + j * 16 + rl;
+            const bool cv = col >= 0 && col < P.n_lo;
+            const int64_t yo = ya + int64_t(min(max(col, 0), P.n_lo - 1)) * P.sYlo;
+            load_frags<TI, KS>(Y + yo, P.sYk, P.K, cv, kq, y[j]);
+        }
+    };
+
+    // No prefetch of the next unit: the registers it would take cost a wave
+    // per SIMD, and more resident waves hide the load latency better.
+    Walk wk = xcd_walk(P.units, 4, wave);
+    for (; wk.u < wk.end; wk.u += wk.step) {
+        load_y(wk.u, ycur);
+        int64_t ya, yc;
+        int t, c0;
+        unit_pos(wk.u, ya, yc, t, c0);
+
+        for (int i = 0; i < M16 / 16; ++i) {
+            acc_t acc[FN];
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc[j] = acc_t{};
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                frag_t b;
+                if constexpr (WIDE) b = *reinterpret_cast<const u4s_t*>(&Bs[(i * 16 + rl) * PB + s * 32 + 8 * kq]);
+                else b = Bs[(s * KSTEP + kq) * PB + i * 16 + rl];
+                // every block runs its MFMAs (blocks outside the run hold
+                // zero fragments): a conditional MFMA costs more in register
+                // copies of the accumulators than the MFMA itself
+#pragma unroll
+                for (int j = 0; j < FN; ++j) acc[j] = smfma<TI>(b, ycur[j][s], acc[j]);
+            }
+#pragma unroll
+            for (int ps = 0; ps < 16 / SR; ++ps) {
+                // Stage layout: FP64 row-major (rows kq of result register ps);
+                // FP32 column-major with the four rows 4kq..4kq+3 of a result
+                // register written as one 16-byte vector.  (Row-major FP32
+                // staging with scalar stores was miscompiled by hipcc for
+                // gfx950: two stores merged into a ds_write2_b32 with a wrong
+                // first offset.)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+                    if constexpr (F64) stg[kq * SP + j * 16 + rl] = acc[j][ps];
+                    else *reinterpret_cast<f4s_t*>(&stg[(j * 16 + rl) * SPC + 4 * kq]) = acc[j];
+                }
+                __builtin_amdgcn_wave_barrier();
+                const int j0 = i * 16 + ps * SR;  // first row of C in this pass
+                if constexpr (MODE == TTM_ROWS_BAND || MODE == TTM_ROWS_BAND1) {
+                    const int nrows = min(SR, P.M - j0);
+                    TA* base = C + yc + int64_t(j0) * P.sCm;
+                    const int len = nrows > 0 ? nrows * P.n_lo : 0;
+                    for (int e = lane; e < len; e += 64) {
+                        const int rr = int(fdiv(uint32_t(e), P.fd_lo));
+                        base[e] = stage_at(rr, e - rr * P.n_lo);
+                    }
+                } else {
+#pragma unroll 4
+                    for (int rr = 0; rr < SR; ++rr) {
+                        const int j = j0 + rr;
+                        if (j >= P.M) break;
+                        TA* rowp = C + yc + int64_t(j) * P.sCm;
+                        int ws = W * t;
+                        if constexpr (MODE == TTM_ROWS_ALIGNED)
+                            ws -= int((reinterpret_cast<uintptr_t>(rowp) & 127) / sizeof(TA));
+                        const int col = ws + lane;
+                        if (col >= 0 && col < P.n_lo) rowp[int64_t(col) * P.sClo] = stage_at(rr, col - c0);
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ launch
 
-template <typename TI, int FM, int FN, int KS, bool TR, int WGM>
+template <typename TI, int FM, int FN, int KS>
 static int stream_launch(const TtmParams& p, int grid, hipStream_t s) {
     constexpr bool WIDE = sizeof(TI) == 2;
     constexpr int KP = KS * SMfma<TI>::KSTEP;
-    constexpr int M16 = WGM * FM * 16;
+    constexpr int M16 = FM * 16;
     constexpr int PB = WIDE ? (KP + 8) : (M16 + (sizeof(TI) == 8 ? 4 : 16));
     const size_t lds = size_t(WIDE ? M16 * PB : KP * PB) * (WIDE ? 2 : sizeof(TI));
-    hipLaunchKernelGGL((ttm_stream_kernel<TI, FM, FN, KS, TR, WGM>), dim3(grid), dim3(256), lds, s, p);
+    hipLaunchKernelGGL((ttm_stream_kernel<TI, FM, FN, KS>), dim3(grid), dim3(256), lds, s, p);
     return hipGetLastError() == hipSuccess ? TLIB_OK : TLIB_EHIP;
 }
 
-// Dispatch over (FM, KS, TRANS); FN follows from the accumulator budget.
-// KS (k-steps) is rounded up to one of the instantiated depths by the planner.
-// fm: total row blocks (1, 4 or 16), all owned by each wave; FN column blocks
-// per wave keep the accumulators at 64 values per lane.
-template <typename TI, int FMT>
-static int stream_fm(const TtmParams& p, int ks, bool tr, int grid, hipStream_t s) {
-    // measured on MI355X: one wave owning all rows of a 16-column strip beats
-    // splitting the rows over the waves, despite the lower occupancy
-    constexpr int WGM = 1;
-    constexpr int FM = FMT;
-    constexpr int FN = FMT >= 16 ? 1 : FMT >= 4 ? 2 : 4;
-#define TLIB_KS_CASE(K)                                                                                      \
-    case K:                                                                                                  \
-        return tr ? stream_launch<TI, FM, FN, K, true, WGM>(p, grid, s)                                      \
-                  : stream_launch<TI, FM, FN, K, false, WGM>(p, grid, s);
+// Dispatch over (FM, KS).  KS (k-steps) is rounded up to one of the
+// instantiated depths by the planner.  fm: total row blocks (1, 4 or 16), all
+// owned by each wave; FN column blocks per wave keep the accumulators at 64
+// values per lane.
+template <typename TI, int FM>
+static int stream_fm(const TtmParams& p, int ks, int grid, hipStream_t s) {
+    constexpr int FN = FM >= 16 ? 1 : FM >= 4 ? 2 : 4;
+#define TLIB_KS_CASE(K) \
+    case K: return stream_launch<TI, FM, FN, K>(p, grid, s);
     if constexpr (sizeof(TI) == 2) {
         switch (ks) {
             TLIB_KS_CASE(1)
@@ -265,20 +416,126 @@ int ttm_stream_ks(int dtype, int k) {
 }
 
 template <typename TI>
-static int stream_dispatch(const TtmParams& p, int fm, int ks, bool tr, int grid, hipStream_t s) {
+static int stream_dispatch(const TtmParams& p, int fm, int ks, int grid, hipStream_t s) {
     switch (fm) {
-        case 1: return stream_fm<TI, 1>(p, ks, tr, grid, s);
-        case 4: return stream_fm<TI, 4>(p, ks, tr, grid, s);
-        default: return stream_fm<TI, 16>(p, ks, tr, grid, s);
+        case 1: return stream_fm<TI, 1>(p, ks, grid, s);
+        case 4: return stream_fm<TI, 4>(p, ks, grid, s);
+        default: return stream_fm<TI, 16>(p, ks, grid, s);
     }
 }
 
 int launch_ttm_stream(int dtype, const TtmParams& p, int fm, int ks, bool trans, int grid, hipStream_t s) {
+    if (!trans) return TLIB_EINVAL;  // C strided along j: launch_ttm_rows
     switch (dtype) {
-        case TLIB_F64: return stream_dispatch<double>(p, fm, ks, trans, grid, s);
-        case TLIB_F32: return stream_dispatch<float>(p, fm, ks, trans, grid, s);
-        case TLIB_BF16: return stream_dispatch<bf16_t>(p, fm, ks, trans, grid, s);
-        case TLIB_F16: return stream_dispatch<f16_t>(p, fm, ks, trans, grid, s);
+        case TLIB_F64: return stream_dispatch<double>(p, fm, ks, grid, s);
+        case TLIB_F32: return stream_dispatch<float>(p, fm, ks, grid, s);
+        case TLIB_BF16: return stream_dispatch<bf16_t>(p, fm, ks, grid, s);
+        case TLIB_F16: return stream_dispatch<f16_t>(p, fm, ks, grid, s);
+    }
+    return TLIB_EDTYPE;
+}
+
+// Row-streaming kernel: staged column blocks per mode.
+template <typename TI> constexpr int rows_fn(int mode) {
+    return mode == TTM_ROWS_ALIGNED ? (64 + 128 / int(sizeof(typename AccOf<TI>::type))) / 16
+           : mode == TTM_ROWS_PLAIN ? 4
+           : mode == TTM_ROWS_BAND  ? 2
+                                    : 1;
+}
+
+template <typename TI>
+static int64_t rows_lds(int mode, int m, int ks) {
+    using TA = typename AccOf<TI>::type;
+    constexpr bool WIDE = sizeof(TI) == 2;
+    constexpr bool F64 = std::is_same<TI, double>::value;
+    const int kp = ks * SMfma<TI>::KSTEP;
+    const int m16 = (m + 15) & ~15;
+    const int pb = WIDE ? (kp + 8) : (m16 + (F64 ? 4 : 16));
+    const int64_t bbytes = (int64_t(WIDE ? m16 * pb : kp * pb) * (WIDE ? 2 : int(sizeof(TI))) + 15) & ~int64_t(15);
+    const int fn = rows_fn<TI>(mode);
+    const int stg = F64 ? 4 * (fn * 16 + 2) : fn * 16 * 20;  // per wave, as in ttm_rows_kernel
+    return bbytes + int64_t(4) * stg * int64_t(sizeof(TA));
+}
+
+int64_t ttm_rows_lds(int dtype, int mode, int m, int ks) {
+    switch (dtype) {
+        case TLIB_F64: return rows_lds<double>(mode, m, ks);
+        case TLIB_F32: return rows_lds<float>(mode, m, ks);
+        default: return rows_lds<bf16_t>(mode, m, ks);
+    }
+}
+
+// k-step depths instantiated for the row kernel: aligned windows keep
+// FN * KS <= 36 fragments in registers.
+int ttm_rows_ks(int dtype, int mode, int k) {
+    if (dtype == TLIB_BF16 || dtype == TLIB_F16) return k <= 32 ? 1 : k <= 64 ? 2 : 0;
+    const int ks = (k + 3) / 4;
+    static const int depths[] = {1, 2, 3, 4, 5, 6, 8, 10};
+    const int cap = mode == TTM_ROWS_ALIGNED ? 6 : 10;
+    for (int d : depths)
+        if (ks <= d) return d <= cap ? d : 0;
+    return 0;
+}
+
+template <typename TI, int MODE, int KS>
+static int rows_launch(const TtmRowParams& p, int grid, hipStream_t s) {
+    constexpr int FN = rows_fn<TI>(MODE);
+    const size_t lds = size_t(rows_lds<TI>(MODE, p.M, KS));
+    hipLaunchKernelGGL((ttm_rows_kernel<TI, FN, KS, MODE>), dim3(grid), dim3(256), lds, s, p);
+    return hipGetLastError() == hipSuccess ? TLIB_OK : TLIB_EHIP;
+}
+
+template <typename TI, int MODE>
+static int rows_ks(const TtmRowParams& p, int ks, int grid, hipStream_t s) {
+#define TLIB_KS_CASE(K) \
+    case K: return rows_launch<TI, MODE, K>(p, grid, s);
+    if constexpr (sizeof(TI) == 2) {
+        switch (ks) {
+            TLIB_KS_CASE(1)
+            TLIB_KS_CASE(2)
+        }
+    } else if constexpr (MODE == TTM_ROWS_ALIGNED) {
+        switch (ks) {
+            TLIB_KS_CASE(1)
+            TLIB_KS_CASE(2)
+            TLIB_KS_CASE(3)
+            TLIB_KS_CASE(4)
+            TLIB_KS_CASE(5)
+            TLIB_KS_CASE(6)
+        }
+    } else {
+        switch (ks) {
+            TLIB_KS_CASE(1)
+            TLIB_KS_CASE(2)
+            TLIB_KS_CASE(3)
+            TLIB_KS_CASE(4)
+            TLIB_KS_CASE(5)
+            TLIB_KS_CASE(6)
+            TLIB_KS_CASE(8)
+            TLIB_KS_CASE(10)
+        }
+    }
+#undef TLIB_KS_CASE
+    return TLIB_EINVAL;
+}
+
+template <typename TI>
+static int rows_mode(const TtmRowParams& p, int mode, int ks, int grid, hipStream_t s) {
+    switch (mode) {
+        case TTM_ROWS_PLAIN: return rows_ks<TI, TTM_ROWS_PLAIN>(p, ks, grid, s);
+        case TTM_ROWS_ALIGNED: return rows_ks<TI, TTM_ROWS_ALIGNED>(p, ks, grid, s);
+        case TTM_ROWS_BAND: return rows_ks<TI, TTM_ROWS_BAND>(p, ks, grid, s);
+        case TTM_ROWS_BAND1: return rows_ks<TI, TTM_ROWS_BAND1>(p, ks, grid, s);
+    }
+    return TLIB_EINVAL;
+}
+
+int launch_ttm_rows(int dtype, const TtmRowParams& p, int mode, int ks, int grid, hipStream_t s) {
+    switch (dtype) {
+        case TLIB_F64: return rows_mode<double>(p, mode, ks, grid, s);
+        case TLIB_F32: return rows_mode<float>(p, mode, ks, grid, s);
+        case TLIB_BF16: return rows_mode<bf16_t>(p, mode, ks, grid, s);
+        case TLIB_F16: return rows_mode<f16_t>(p, mode, ks, grid, s);
     }
     return TLIB_EDTYPE;
 }
