@@ -779,7 +779,10 @@ static int ttm_dispatch(const Ten& a, const Ten& bm, int mi, const Ten& c, int p
                                : mode == TTM_ROWS_PLAIN ? (n_lo + 63) / 64
                                                         : 1;
             const int64_t units = ncols / n_lo * tc;
-            if (ks > 0 && lds <= 65536 && units < (int64_t(1) << 31) && fill_grp(R.gh, dn + 1, ndn - 1, 0, 1)) {
+            // a 16-row block of C is addressed with 32-bit buffer offsets
+            const int64_t blk_bytes = (16 * c.w[mi] + n_lo * sclo) * int64_t(esize(acc_dtype(a.dtype)));
+            if (ks > 0 && lds <= 65536 && units < (int64_t(1) << 31) && blk_bytes < (int64_t(1) << 31) &&
+                fill_grp(R.gh, dn + 1, ndn - 1, 0, 1)) {
                 R.X = bm.data;
                 R.Y = a.data;
                 R.C = c.data;

@@ -26,6 +26,7 @@ typedef float f4s_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8s_t __attribute__((ext_vector_type(8)));
 typedef _Float16 h8s_t __attribute__((ext_vector_type(8)));
 typedef uint32_t u4s_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u2s_t __attribute__((ext_vector_type(2)));
 
 template <typename TI> struct SMfma {
     using acc_t = f4s_t;
@@ -217,10 +218,14 @@ __global__ __launch_bounds__(256) void ttm_stream_kernel(TtmParams P) {
 // Row-streaming TTM for C strided along j (see TtmRowParams).  B (M x K,
 // zero-padded to 16-row blocks and the MFMA k-step) is staged in LDS once per
 // workgroup; each of the four waves then walks its own (run, chunk) units: it
-// loads the chunk's A fragments (16*FN columns, all k) into registers, issuing
-// the loads of its next unit first, and for every 16-row block of C runs the
-// MFMAs, stages the block in its own LDS rows and writes them back as whole
-// 64-column windows (or, in band mode, as one linear range).
+// loads the chunk's A fragments (16*FN columns, all k) into registers and, for
+// every 16-row block of C, runs the MFMAs, stages the block in its own LDS rows
+// and writes them back as whole 64-column windows (or, in band mode, as one
+// linear range).  Stores are raw buffer stores whose lanes outside the run or
+// past the last row get an out-of-range offset, which the buffer's range
+// check drops: the store sequence has no branches.  (Software-pipelining the
+// MFMAs of the next row block into the stores of this one, with or without
+// scheduling barriers, measured no faster on MI355X.)
 template <typename TI, int FN, int KS, int MODE>
 __global__ __launch_bounds__(256) void ttm_rows_kernel(TtmRowParams P) {
     using TA = typename AccOf<TI>::type;
@@ -238,13 +243,15 @@ __global__ __launch_bounds__(256) void ttm_rows_kernel(TtmRowParams P) {
     constexpr int SP = FN * 16 + 2;              // FP64 staging: row pitch
     constexpr int SPC = 20;                      // FP32 staging: column pitch (16-byte aligned)
     constexpr int STG = F64 ? SR * SP : FN * 16 * SPC;  // staged elements per wave
+    constexpr bool BAND = MODE == TTM_ROWS_BAND || MODE == TTM_ROWS_BAND1;
+    constexpr uint32_t OOB = 0x80000000u;       // buffer offset past every range: store dropped
     using RT = typename std::conditional<WIDE, uint16_t, TI>::type;
     static_assert(MODE != TTM_ROWS_ALIGNED || FN * 16 >= W + L, "aligned windows need W + L staged columns");
     static_assert(MODE != TTM_ROWS_PLAIN || FN * 16 >= W, "plain windows need W staged columns");
 
     extern __shared__ __align__(16) unsigned char smem[];
     // wave index through readfirstlane, so that everything derived from it
-    // (unit, run, chunk, block activity) is known to be wave-uniform
+    // (unit, run, chunk) is known to be wave-uniform
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int rl = lane & 15, kq = lane >> 4;
     const int M16 = (P.M + 15) & ~15;
@@ -294,69 +301,98 @@ __global__ __launch_bounds__(256) void ttm_rows_kernel(TtmRowParams P) {
             load_frags<TI, KS>(Y + yo, P.sYk, P.K, cv, kq, y[j]);
         }
     };
-
-    // No prefetch of the next unit: the registers it would take cost a wave
-    // per SIMD, and more resident waves hide the load latency better.
+    // MFMAs of one 16-row block, one k-step at a time.  Every column block
+    // runs (blocks outside the run hold zero fragments: a conditional MFMA
+    // costs more in register copies of the accumulators than the MFMA
+    // itself).
+    auto mfma_step = [&](int i, int s, acc_t (&acc)[FN]) {
+        const int ib = i;
+        if (s == 0) {
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc[j] = acc_t{};
+        }
+        frag_t b;
+        if constexpr (WIDE) b = *reinterpret_cast<const u4s_t*>(&Bs[(ib * 16 + rl) * PB + s * 32 + 8 * kq]);
+        else b = Bs[(s * KSTEP + kq) * PB + ib * 16 + rl];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[j] = smfma<TI>(b, ycur[j][s], acc[j]);
+    };
+    // Stage and store one 16-row block in four pieces of four rows.  The
+    // buffer range of the block covers its rows below M and the run's
+    // columns; every other lane's offset is out of range.
+    constexpr int NPC = 4;
+    auto store_piece = [&](int i, int pc, const acc_t (&acc)[FN], int64_t yc, int t, int c0) {
+        const int j0 = i * 16;
+        const int nrows = max(0, min(16, P.M - j0));
+        TA* base = C + yc + int64_t(j0) * P.sCm;
+        // Every lane also checks its row against nrows: with m = 1 the stride
+        // of j is arbitrary, so rows past the last one can land inside the
+        // range.  The range then only backs up the lane predicates.
+        const uint32_t live = nrows > 0 ? 0xffffffffu : 0u;
+        const uint32_t nbytes =
+            live & (BAND ? uint32_t(nrows * P.n_lo) * uint32_t(sizeof(TA))
+                         : uint32_t((int64_t(nrows - 1) * P.sCm + int64_t(P.n_lo - 1) * P.sClo + 1) *
+                                    int64_t(sizeof(TA))));
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(base, 0, int(nbytes), 0x00020000);
+        // Stage layout: FP64 row-major, the four rows kq of result register
+        // pc; FP32 column-major with the four rows 4kq..4kq+3 of a result
+        // register written as one 16-byte vector, all sixteen rows at piece 0.
+        // (Row-major FP32 staging with scalar stores was miscompiled by hipcc
+        // for gfx950: two stores merged into a ds_write2_b32 with a wrong
+        // first offset.)
+        if (F64 || pc == 0) {
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                if constexpr (F64) stg[kq * SP + j * 16 + rl] = acc[j][pc];
+                else *reinterpret_cast<f4s_t*>(&stg[(j * 16 + rl) * SPC + 4 * kq]) = acc[j];
+            }
+        }
+        const int r0 = F64 ? 0 : 4 * pc;  // first staged row of this piece
+        auto put = [&](TA v, bool ok, uint32_t byte_off) {
+            const uint32_t off = ok ? byte_off : OOB;
+            if constexpr (F64)
+                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2s_t, v), rs, int(off), 0, 0);
+            else
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rs, int(off), 0, 0);
+        };
+        if constexpr (BAND) {
+            // rows 4pc .. 4pc+3 of the block are one linear range
+            const int e0 = 4 * pc * P.n_lo;
+#pragma unroll
+            for (int it = 0; it < (4 * 16 * FN + 63) / 64; ++it) {
+                const int e = it * 64 + lane;
+                const int rr = int(fdiv(uint32_t(e), P.fd_lo));
+                const bool ok = e < 4 * P.n_lo && 4 * pc + rr < nrows;
+                const TA v = stage_at(ok ? r0 + rr : 0, ok ? e - rr * P.n_lo : 0);
+                put(v, ok, uint32_t(e0 + e) * uint32_t(sizeof(TA)));
+            }
+        } else {
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int jr = 4 * pc + rr;  // row within the block
+                int ws = W * t;
+                if constexpr (MODE == TTM_ROWS_ALIGNED)
+                    ws -= int((reinterpret_cast<uintptr_t>(base + int64_t(jr) * P.sCm) & 127) / sizeof(TA));
+                const int col = ws + lane;
+                const bool ok = col >= 0 && col < P.n_lo && jr < nrows;
+                const TA v = stage_at(r0 + rr, ok ? col - c0 : 0);
+                put(v, ok, uint32_t((int64_t(jr) * P.sCm + int64_t(col) * P.sClo) * int64_t(sizeof(TA))));
+            }
+        }
+    };
     Walk wk = xcd_walk(P.units, 4, wave);
+    const int nb = M16 / 16;
     for (; wk.u < wk.end; wk.u += wk.step) {
         load_y(wk.u, ycur);
         int64_t ya, yc;
         int t, c0;
         unit_pos(wk.u, ya, yc, t, c0);
-
-        for (int i = 0; i < M16 / 16; ++i) {
-            acc_t acc[FN];
+        acc_t acc[FN];
+        for (int i = 0; i < nb; ++i) {
 #pragma unroll
-            for (int j = 0; j < FN; ++j) acc[j] = acc_t{};
+            for (int q = 0; q < KS; ++q) mfma_step(i, q, acc);
 #pragma unroll
-            for (int s = 0; s < KS; ++s) {
-                frag_t b;
-                if constexpr (WIDE) b = *reinterpret_cast<const u4s_t*>(&Bs[(i * 16 + rl) * PB + s * 32 + 8 * kq]);
-                else b = Bs[(s * KSTEP + kq) * PB + i * 16 + rl];
-                // every block runs its MFMAs (blocks outside the run hold
-                // zero fragments): a conditional MFMA costs more in register
-                // copies of the accumulators than the MFMA itself
-#pragma unroll
-                for (int j = 0; j < FN; ++j) acc[j] = smfma<TI>(b, ycur[j][s], acc[j]);
-            }
-#pragma unroll
-            for (int ps = 0; ps < 16 / SR; ++ps) {
-                // Stage layout: FP64 row-major (rows kq of result register ps);
-                // FP32 column-major with the four rows 4kq..4kq+3 of a result
-                // register written as one 16-byte vector.  (Row-major FP32
-                // staging with scalar stores was miscompiled by hipcc for
-                // gfx950: two stores merged into a ds_write2_b32 with a wrong
-                // first offset.)
-#pragma unroll
-                for (int j = 0; j < FN; ++j) {
-                    if constexpr (F64) stg[kq * SP + j * 16 + rl] = acc[j][ps];
-                    else *reinterpret_cast<f4s_t*>(&stg[(j * 16 + rl) * SPC + 4 * kq]) = acc[j];
-                }
-                __builtin_amdgcn_wave_barrier();
-                const int j0 = i * 16 + ps * SR;  // first row of C in this pass
-                if constexpr (MODE == TTM_ROWS_BAND || MODE == TTM_ROWS_BAND1) {
-                    const int nrows = min(SR, P.M - j0);
-                    TA* base = C + yc + int64_t(j0) * P.sCm;
-                    const int len = nrows > 0 ? nrows * P.n_lo : 0;
-                    for (int e = lane; e < len; e += 64) {
-                        const int rr = int(fdiv(uint32_t(e), P.fd_lo));
-                        base[e] = stage_at(rr, e - rr * P.n_lo);
-                    }
-                } else {
-#pragma unroll 4
-                    for (int rr = 0; rr < SR; ++rr) {
-                        const int j = j0 + rr;
-                        if (j >= P.M) break;
-                        TA* rowp = C + yc + int64_t(j) * P.sCm;
-                        int ws = W * t;
-                        if constexpr (MODE == TTM_ROWS_ALIGNED)
-                            ws -= int((reinterpret_cast<uintptr_t>(rowp) & 127) / sizeof(TA));
-                        const int col = ws + lane;
-                        if (col >= 0 && col < P.n_lo) rowp[int64_t(col) * P.sClo] = stage_at(rr, col - c0);
-                    }
-                }
-                __builtin_amdgcn_wave_barrier();
-            }
+            for (int q = 0; q < NPC; ++q) store_piece(i, q, acc, yc, t, c0);
         }
     }
 }

@@ -127,3 +127,26 @@ def test_autotune_ttm_ttt(T):
     finally:
         T.set_autotune(prev)
         T.autotune_clear()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_ttm_single_row_stays_inside_output(T, dtype):
+    """m = 1: the stride of j is free, so the row kernel must drop the rows of
+    its 16-row blocks past the first by predicate; C sits at the start of a
+    larger buffer whose tail must stay untouched."""
+    import torch
+    g = synth.rng(24, 0)
+    shape, q = (33, 29, 17), 1
+    X = synth.uniform(shape, g)
+    B = synth.uniform((1, shape[0]), g)
+    Ad, Bd = to_gpu(X, None, dtype), to_gpu(B, None, dtype)
+    n = 29 * 17
+    big = torch.full((n + 4096,), float("nan"), dtype=T.acc_dtype(Ad.dtype), device="cuda")
+    C = torch.as_strided(big, (1, 29, 17), (1, 1, 29))
+    plan = T.plan(T.ttm, Ad, Bd, q, out=C)
+    assert "ttm rows" in plan, plan
+    T.ttm(Ad, Bd, q, out=C)
+    torch.cuda.synchronize()
+    ref = oracle.ttm(oracle.materialize(round_to(X, dtype)), round_to(B, dtype), q)
+    assert_close(to_np(C), ref, TOL[dtype], plan)
+    assert torch.isnan(big[n:]).all(), "the kernel wrote past the output"
