@@ -774,7 +774,15 @@ static int ttm_dispatch(const Ten& a, const Ten& bm, int mi, const Ten& c, int p
                 mode = TTM_ROWS_PLAIN;
             }
             const int ks = ttm_rows_ks(a.dtype, mode, int(std::min<int64_t>(Kr, 1 << 20)));
-            const int64_t lds = ks > 0 ? ttm_rows_lds(a.dtype, mode, int(Mr), ks) : INT64_MAX;
+            // rows of B per workgroup: all of them if B's slice fits in LDS,
+            // else halve into row groups
+            int mr = int((Mr + 15) / 16 * 16);
+            int64_t lds = ks > 0 ? ttm_rows_lds(a.dtype, mode, mr, ks) : INT64_MAX;
+            while (ks > 0 && lds > 65536 && mr > 16) {
+                mr = (mr / 2 + 15) / 16 * 16;
+                lds = ttm_rows_lds(a.dtype, mode, mr, ks);
+            }
+            const int nrg = int((Mr + mr - 1) / mr);
             const int64_t tc = mode == TTM_ROWS_ALIGNED ? (n_lo + lpc - 1 + 63) / 64
                                : mode == TTM_ROWS_PLAIN ? (n_lo + 63) / 64
                                                         : 1;
@@ -799,15 +807,19 @@ static int ttm_dispatch(const Ten& a, const Ten& bm, int mi, const Ten& c, int p
                 R.units = units;
                 R.fd_tc = make_fastdiv(uint32_t(tc));
                 R.fd_lo = make_fastdiv(uint32_t(n_lo));
+                R.mr = mr;
+                R.nrg = nrg;
                 const int per_cu = int(std::max<int64_t>(1, std::min<int64_t>(4, 160 * 1024 / lds)));
-                const int grid = int(std::max<int64_t>(1, std::min<int64_t>((units + 3) / 4, 256 * per_cu)));
+                int64_t g0 = std::max<int64_t>(1, std::min<int64_t>((units + 3) / 4, 256 * per_cu / nrg));
+                if (nrg > 1) g0 = (g0 + 7) / 8 * 8;  // the row-group mapping needs whole XCD rounds
+                const int grid = int(g0 * nrg);
                 plan_note("ttm rows dtype=%s mode=%s M=%lld K=%lld n_lo=%lld runs=%lld chunks=%lld ks=%d lds=%lld "
-                          "grid=%d",
+                          "rowgroups=%dx%d grid=%d",
                           dname(a.dtype),
                           mode == TTM_ROWS_BAND ? "band" : mode == TTM_ROWS_BAND1 ? "band1"
                                                  : mode == TTM_ROWS_ALIGNED ? "aligned" : "plain",
                           (long long)Mr, (long long)Kr, (long long)n_lo, (long long)(ncols / n_lo), (long long)tc, ks,
-                          (long long)lds, grid);
+                          (long long)lds, nrg, mr, grid);
                 if (g_plan_only) return TLIB_OK;
                 int rc2 = launch_ttm_rows(a.dtype, R, mode, ks, grid, hipStream_t(stream));
                 return rc2 ? fail(rc2, "ttm: launch failed") : TLIB_OK;

@@ -129,6 +129,8 @@ struct TtmRowParams {
     int64_t units;  // runs * Tc
     FastDiv fd_tc, fd_lo;
     Grp gh;
+    int32_t mr;   // rows of B served by one workgroup (multiple of 16)
+    int32_t nrg;  // row groups, ceil(M / mr); the grid is a multiple of 8 * nrg when nrg > 1
 };
 
 // Work table of a grouped launch (k_batch.hip): a header followed by items.
@@ -169,7 +171,8 @@ int launch_gemm(int dtype, int tile, const GemmParams& p, hipStream_t s);
 // fm: row blocks (1, 4 or 16); ks: k-steps from ttm_stream_ks (0 = unsupported)
 int launch_ttm_stream(int dtype, const TtmParams& p, int fm, int ks, bool trans, int grid, hipStream_t s);
 int ttm_stream_ks(int dtype, int k);
-// Row-streaming TTM (TtmRowParams); ks from ttm_rows_ks, lds from ttm_rows_lds.
+// Row-streaming TTM (TtmRowParams); ks from ttm_rows_ks, lds from ttm_rows_lds
+// (m = rows per workgroup, p.mr).
 int launch_ttm_rows(int dtype, const TtmRowParams& p, int mode, int ks, int grid, hipStream_t s);
 int ttm_rows_ks(int dtype, int mode, int k);
 int64_t ttm_rows_lds(int dtype, int mode, int m, int ks);

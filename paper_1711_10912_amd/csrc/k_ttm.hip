@@ -97,8 +97,8 @@ __device__ __forceinline__ void load_frags(const TI* y, int64_t sk, int K, bool 
 struct Walk {
     int64_t u, end, step;
 };
-__device__ __forceinline__ Walk xcd_walk(int64_t units, int workers, int worker) {
-    const int G = gridDim.x, ng = G < 8 ? G : 8, xg = blockIdx.x % ng, ix = blockIdx.x / ng;
+__device__ __forceinline__ Walk xcd_walk(int64_t units, int workers, int worker, int blk, int G) {
+    const int ng = G < 8 ? G : 8, xg = blk % ng, ix = blk / ng;
     const int nx = (G - xg + ng - 1) / ng;
     Walk w;
     w.end = int64_t(xg + 1) * units / ng;
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(256) void ttm_stream_kernel(TtmParams P) {
         }
     };
 
-    Walk wk = xcd_walk(T, 1, 0);
+    Walk wk = xcd_walk(T, 1, 0, blockIdx.x, gridDim.x);
     if (wk.u < wk.end) load_y(wk.u, ycur);
     for (; wk.u < wk.end; wk.u += wk.step) {
         const int64_t tn = wk.u + wk.step;
@@ -254,7 +254,16 @@ __global__ __launch_bounds__(256) void ttm_rows_kernel(TtmRowParams P) {
     // (unit, run, chunk) is known to be wave-uniform
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int rl = lane & 15, kq = lane >> 4;
-    const int M16 = (P.M + 15) & ~15;
+    // Row groups: with P.nrg > 1 each workgroup serves the P.mr rows
+    // [rg*mr, rg*mr + mr) of B and C, so that B's slice fits in LDS.  The
+    // grid is a multiple of 8*nrg; the nrg workgroups that share a block
+    // index for the walk sit on one XCD and read the same A chunks through
+    // its L2.
+    const int rg = P.nrg > 1 ? int(blockIdx.x / 8) % P.nrg : 0;
+    const int wblk = P.nrg > 1 ? int(blockIdx.x / (8 * P.nrg)) * 8 + int(blockIdx.x % 8) : int(blockIdx.x);
+    const int wgrid = P.nrg > 1 ? int(gridDim.x) / P.nrg : int(gridDim.x);
+    const int row0 = rg * P.mr;                          // first row of B / C served here
+    const int M16 = (min(P.M - row0, P.mr) + 15) & ~15;  // rows staged, padded to 16
     const int PB = WIDE ? (KP + 8) : (M16 + (F64 ? 4 : 16));
     RT* Bs = reinterpret_cast<RT*>(smem);
     const int bbytes = ((WIDE ? M16 * PB : KP * PB) * int(sizeof(RT)) + 15) & ~15;
@@ -269,8 +278,8 @@ __global__ __launch_bounds__(256) void ttm_rows_kernel(TtmRowParams P) {
         if constexpr (WIDE) { m = e / KP; k = e - m * KP; }
         else { k = e / M16; m = e - k * M16; }
         RT v = RT(0);
-        if (m < P.M && k < P.K) {
-            const TI* src = X + int64_t(m) * P.sXm + int64_t(k) * P.sXk;
+        if (row0 + m < P.M && k < P.K) {
+            const TI* src = X + int64_t(row0 + m) * P.sXm + int64_t(k) * P.sXk;
             if constexpr (WIDE) v = uint16_t(raw16(src));
             else v = *src;
         }
@@ -322,7 +331,7 @@ __global__ __launch_bounds__(256) void ttm_rows_kernel(TtmRowParams P) {
     // columns; every other lane's offset is out of range.
     constexpr int NPC = 4;
     auto store_piece = [&](int i, int pc, const acc_t (&acc)[FN], int64_t yc, int t, int c0) {
-        const int j0 = i * 16;
+        const int j0 = row0 + i * 16;
         const int nrows = max(0, min(16, P.M - j0));
         TA* base = C + yc + int64_t(j0) * P.sCm;
         // Every lane also checks its row against nrows: with m = 1 the stride
@@ -380,7 +389,7 @@ __global__ __launch_bounds__(256) void ttm_rows_kernel(TtmRowParams P) {
             }
         }
     };
-    Walk wk = xcd_walk(P.units, 4, wave);
+    Walk wk = xcd_walk(P.units, 4, wave, wblk, wgrid);
     const int nb = M16 / 16;
     for (; wk.u < wk.end; wk.u += wk.step) {
         load_y(wk.u, ycur);
@@ -516,7 +525,7 @@ int ttm_rows_ks(int dtype, int mode, int k) {
 template <typename TI, int MODE, int KS>
 static int rows_launch(const TtmRowParams& p, int grid, hipStream_t s) {
     constexpr int FN = rows_fn<TI>(MODE);
-    const size_t lds = size_t(rows_lds<TI>(MODE, p.M, KS));
+    const size_t lds = size_t(rows_lds<TI>(MODE, p.mr, KS));
     hipLaunchKernelGGL((ttm_rows_kernel<TI, FN, KS, MODE>), dim3(grid), dim3(256), lds, s, p);
     return hipGetLastError() == hipSuccess ? TLIB_OK : TLIB_EHIP;
 }

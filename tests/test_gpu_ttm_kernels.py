@@ -150,3 +150,29 @@ def test_ttm_single_row_stays_inside_output(T, dtype):
     ref = oracle.ttm(oracle.materialize(round_to(X, dtype)), round_to(B, dtype), q)
     assert_close(to_np(C), ref, TOL[dtype], plan)
     assert torch.isnan(big[n:]).all(), "the kernel wrote past the output"
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("m", [256, 200])
+def test_ttm_row_groups(T, dtype, m):
+    """k = 36 with m = 200..256: B's slice does not fit in one workgroup's
+    LDS, so the row kernel splits the rows of B and C into groups served by
+    different workgroups (ragged last group for m = 200)."""
+    import torch
+    g = synth.rng(25, m)
+    shape, q = (37, 36, 11), 2
+    X = synth.uniform(shape, g)
+    B = synth.uniform((m, shape[q - 1]), g)
+    Ad, Bd = to_gpu(X, None, dtype), to_gpu(B, None, dtype)
+    sc = list(shape)
+    sc[q - 1] = m
+    C = T.empty(sc, None, T.acc_dtype(Ad.dtype), Ad.device)
+    plan = T.plan(T.ttm, Ad, Bd, q, out=C)
+    assert "ttm rows" in plan, plan
+    if dtype == "f64":
+        assert "rowgroups=1x" not in plan, plan
+    C.fill_(float("nan"))
+    T.ttm(Ad, Bd, q, out=C)
+    torch.cuda.synchronize()
+    ref = oracle.ttm(oracle.materialize(round_to(X, dtype)), round_to(B, dtype), q)
+    assert_close(to_np(C), ref, TOL[dtype], plan)
