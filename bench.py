@@ -394,8 +394,11 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--quick", action="store_true", help="p = 3 and 7 only (for profiling runs)")
-    ap.add_argument("--autotune", default="on", choices=("on", "off"),
-                    help="tune the TTM/TTT kernel choice per call shape in the first warmup step")
+    ap.add_argument("--autotune", default="on", choices=("on", "off", "load"),
+                    help="on: tune the TTM/TTT kernel choice per call shape in the first warmup step; "
+                         "load: use the choices saved in --autotune-table (no tuning)")
+    ap.add_argument("--autotune-table", default="",
+                    help="with --autotune on: save the tuned table here; with load: read it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cases-out", default="", help="write per-case timings (JSON lines) here")
     ap.add_argument("--workload", default="sweep", choices=("sweep", "serve"),
@@ -435,8 +438,13 @@ def main():
     print("bench: %d calls per step" % len(cases), file=sys.stderr, flush=True)
     # Autotuning (kernel choice per call shape) happens in the first warmup
     # step; the timed steps only use stored choices.
-    tune = "on" if args.autotune == "on" and args.warmup > 0 else "off"
-    T.set_autotune(tune)
+    if args.autotune == "load":
+        T.autotune_load(args.autotune_table)
+        tune = "loaded"
+        T.set_autotune("frozen")
+    else:
+        tune = "on" if args.autotune == "on" and args.warmup > 0 else "off"
+        T.set_autotune(tune)
     t_tune = time.perf_counter()
     for w in range(args.warmup):
         run_step(cases, torch, None)
@@ -445,6 +453,8 @@ def main():
             t_tune = time.perf_counter() - t_tune
             if tune == "on":
                 T.set_autotune("frozen")
+                if args.autotune_table:
+                    T.autotune_save(args.autotune_table)
     torch.cuda.synchronize()
     for c in cases:
         c.kernel = _kernel_label(c.planfn())

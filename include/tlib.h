@@ -236,6 +236,14 @@ const char* tlib_last_plan(void);
 int tlib_set_autotune(int mode);  /* returns the previous mode, or -1 (and changes nothing) for an unknown mode */
 int64_t tlib_autotune_entries(void);
 void tlib_autotune_clear(void);
+/* The table as text, one "<choice> <call shape>" line per entry: save writes
+ * it to `path` (TLIB_EINVAL if the file cannot be written); load adds the
+ * entries of such a file to the table (TLIB_EINVAL if it cannot be read or a
+ * line is malformed; entries before the bad line are kept).  A saved table
+ * lets another process (a profiler run, a server restart) reuse the choices
+ * without tuning again. */
+int tlib_autotune_save(const char* path);
+int tlib_autotune_load(const char* path);
 
 /* Library version string. */
 const char* tlib_version(void);

@@ -21,7 +21,7 @@ from ._lib import TlibError
 __all__ = [
     "ttv", "ttm", "ttt", "inner", "norm", "add", "scale", "transpose", "times_tensor",
     "times_vectors", "strides", "layout_of", "empty", "TlibError", "plan", "hopm", "tucker",
-    "set_autotune", "autotune_entries", "autotune_clear",
+    "set_autotune", "autotune_entries", "autotune_clear", "autotune_save", "autotune_load",
 ]
 
 _torch = None
@@ -243,6 +243,16 @@ def autotune_entries() -> int:
 
 def autotune_clear() -> None:
     _lib.lib().tlib_autotune_clear()
+
+
+def autotune_save(path: str) -> None:
+    """Write the autotuning table (one "<choice> <call shape>" line per entry)."""
+    _lib.check(_lib.lib().tlib_autotune_save(str(path).encode()))
+
+
+def autotune_load(path: str) -> None:
+    """Add the entries of a saved autotuning table."""
+    _lib.check(_lib.lib().tlib_autotune_load(str(path).encode()))
 
 
 from .drivers import hopm, tucker  # noqa: E402

@@ -21,7 +21,8 @@ EXPORTS = (
     "tlib_server_create", "tlib_server_submit", "tlib_server_drain", "tlib_server_stats",
     "tlib_server_result", "tlib_server_reset_stats", "tlib_server_destroy",
     "tlib_strides_from_layout", "tlib_last_error", "tlib_strerror", "tlib_set_plan_only",
-    "tlib_last_plan", "tlib_set_autotune", "tlib_autotune_entries", "tlib_autotune_clear", "tlib_version",
+    "tlib_last_plan", "tlib_set_autotune", "tlib_autotune_entries", "tlib_autotune_clear", "tlib_autotune_save",
+    "tlib_autotune_load", "tlib_version",
 )
 
 
@@ -122,6 +123,9 @@ def lib():
         L.tlib_autotune_entries.restype = ctypes.c_int64
         L.tlib_autotune_clear.argtypes = []
         L.tlib_autotune_clear.restype = None
+        for f in ("tlib_autotune_save", "tlib_autotune_load"):
+            getattr(L, f).argtypes = [ctypes.c_char_p]
+            getattr(L, f).restype = ctypes.c_int
         L.tlib_version.restype = ctypes.c_char_p
         L.tlib_version.argtypes = []
         _lib = L

@@ -854,6 +854,43 @@ void tlib_autotune_clear(void) {
     g_tune.clear();
 }
 
+int tlib_autotune_save(const char* path) {
+    begin_call();
+    if (!path) return fail(TLIB_EINVAL, "autotune_save: null path");
+    FILE* f = fopen(path, "w");
+    if (!f) return fail(TLIB_EINVAL, "autotune_save: cannot write %s", path);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (const auto& kv : g_tune) fprintf(f, "%d %s\n", kv.second, kv.first.c_str());
+    }
+    const bool ok = fclose(f) == 0;
+    return ok ? TLIB_OK : fail(TLIB_EINVAL, "autotune_save: write to %s failed", path);
+}
+
+int tlib_autotune_load(const char* path) {
+    begin_call();
+    if (!path) return fail(TLIB_EINVAL, "autotune_load: null path");
+    FILE* f = fopen(path, "r");
+    if (!f) return fail(TLIB_EINVAL, "autotune_load: cannot read %s", path);
+    char line[4096];
+    int rc = TLIB_OK, lineno = 0;
+    while (fgets(line, sizeof(line), f)) {
+        ++lineno;
+        size_t n = strlen(line);
+        while (n > 0 && (line[n - 1] == '\n' || line[n - 1] == '\r')) line[--n] = 0;
+        if (n == 0) continue;
+        int pick = 0, used = 0;
+        if (sscanf(line, "%d %n", &pick, &used) != 1 || used <= 0 || line[used] == 0 || n == sizeof(line) - 1) {
+            rc = fail(TLIB_EINVAL, "autotune_load: %s line %d is malformed", path, lineno);
+            break;
+        }
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[std::string(line + used)] = pick;
+    }
+    fclose(f);
+    return rc;
+}
+
 int tlib_ttm(const tlib_tensor* A, const tlib_tensor* B, int32_t m, const tlib_tensor* C,
              void* stream) {
     begin_call();

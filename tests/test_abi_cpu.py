@@ -172,3 +172,34 @@ def test_binding_refuses_cpu_tensors():
     A = torch.zeros(3, 4)
     with pytest.raises(_lib.TlibError):
         T.ttv(A, torch.zeros(4), 2)
+
+
+def test_autotune_controls(tmp_path):
+    """Autotune mode switch, table save/load round trip and load errors
+    (no GPU: plan-only calls never tune)."""
+    import paper_1711_10912_amd as T
+    L = _lib.lib()
+    assert L.tlib_set_autotune(7) == -1          # unknown mode: unchanged
+    prev = T.set_autotune("frozen")
+    try:
+        assert T.set_autotune("on") == "frozen"
+        T.autotune_clear()
+        assert T.autotune_entries() == 0
+        tab = tmp_path / "tab.txt"
+        tab.write_text("2 ttm|2|0:3,4/1,5/4,6/20|0:2,7/1,4/7|0:3,4/1,7/4,6/28\n"
+                       "5 ttt|1|1|2|1|2|1:2,3/1,4/3|1:2,4/1,2/4|1:2,3/1,2/3\n")
+        T.autotune_load(str(tab))
+        assert T.autotune_entries() == 2
+        out = tmp_path / "out.txt"
+        T.autotune_save(str(out))
+        assert sorted(out.read_text().splitlines()) == sorted(tab.read_text().splitlines())
+        bad = tmp_path / "bad.txt"
+        bad.write_text("3 ok|line\nnot-a-number key\n")
+        with pytest.raises(T.TlibError):
+            T.autotune_load(str(bad))
+        assert T.autotune_entries() == 3           # the good line before the bad one is kept
+        with pytest.raises(T.TlibError):
+            T.autotune_load(str(tmp_path / "missing.txt"))
+    finally:
+        T.autotune_clear()
+        T.set_autotune(prev)
