@@ -33,6 +33,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "TTM/TTT TFLOP/s & TTV GB/s vs roofline; served p50/p99 latency, req/s"
+HERE = os.path.dirname(os.path.abspath(__file__))
+# kernel choices of the sweep's call shapes, tuned on MI355X (tlib_autotune_save format)
+TUNING_TABLE = os.path.join(HERE, "paper_1711_10912_amd", "tuning", "mi355x_sweep.txt")
 PEAK_HBM = 8.0e12
 PEAK_FLOPS = {"f64": 78.6e12, "f32": 157.3e12, "bf16": 2516.6e12, "f16": 2516.6e12}
 ESZ = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
@@ -394,11 +397,13 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--quick", action="store_true", help="p = 3 and 7 only (for profiling runs)")
-    ap.add_argument("--autotune", default="on", choices=("on", "off", "load"),
-                    help="on: tune the TTM/TTT kernel choice per call shape in the first warmup step; "
-                         "load: use the choices saved in --autotune-table (no tuning)")
-    ap.add_argument("--autotune-table", default="",
-                    help="with --autotune on: save the tuned table here; with load: read it")
+    ap.add_argument("--autotune", default="on", choices=("on", "off"),
+                    help="on: preload --autotune-table, then tune the TTM/TTT kernel choice of every call "
+                         "shape it lacks in the first warmup step; off: the planner's fixed rules")
+    ap.add_argument("--autotune-table", default=TUNING_TABLE,
+                    help="kernel-choice table to preload ('' = none); default: the MI355X table shipped "
+                         "with the package")
+    ap.add_argument("--autotune-save", default="", help="write the table after the first warmup step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cases-out", default="", help="write per-case timings (JSON lines) here")
     ap.add_argument("--workload", default="sweep", choices=("sweep", "serve"),
@@ -438,13 +443,14 @@ def main():
     print("bench: %d calls per step" % len(cases), file=sys.stderr, flush=True)
     # Autotuning (kernel choice per call shape) happens in the first warmup
     # step; the timed steps only use stored choices.
-    if args.autotune == "load":
+    preloaded = 0
+    if args.autotune == "on" and args.autotune_table and os.path.exists(args.autotune_table):
         T.autotune_load(args.autotune_table)
-        tune = "loaded"
-        T.set_autotune("frozen")
-    else:
-        tune = "on" if args.autotune == "on" and args.warmup > 0 else "off"
-        T.set_autotune(tune)
+        preloaded = T.autotune_entries()
+    # new call shapes are tuned in the first warmup step only; without warmup
+    # they take the planner's rules
+    tune = "off" if args.autotune == "off" else ("on" if args.warmup > 0 else "frozen")
+    T.set_autotune(tune)
     t_tune = time.perf_counter()
     for w in range(args.warmup):
         run_step(cases, torch, None)
@@ -453,8 +459,8 @@ def main():
             t_tune = time.perf_counter() - t_tune
             if tune == "on":
                 T.set_autotune("frozen")
-                if args.autotune_table:
-                    T.autotune_save(args.autotune_table)
+    if args.autotune_save:
+        T.autotune_save(args.autotune_save)
     torch.cuda.synchronize()
     for c in cases:
         c.kernel = _kernel_label(c.planfn())
@@ -557,7 +563,8 @@ def main():
                                "A{3,4}<->B{1,2}, 3 A layouts, f32/bf16/f16" + (" [quick: p=3,7 only]" if args.quick else ""),
                    "calls_per_step": len(cases)},
         "roofline_frac_step": round(tot_ideal / (ms_per_step * 1e-3), 4),
-        "autotune": {"mode": tune, "entries": T.autotune_entries(),
+        "autotune": {"mode": tune, "preloaded": preloaded, "entries": T.autotune_entries(),
+                     "table": os.path.relpath(args.autotune_table, HERE) if preloaded else None,
                      "first_warmup_step_s": round(t_tune, 2) if args.warmup > 0 else None},
         "roofline": roof,
         "breakdown": breakdown,

@@ -385,9 +385,10 @@ static int run_ttv(const Ten& a, const Ten& b, int mi, const Ten& c, hipStream_t
 // Per-key choice among the launch candidates of one call shape (op, modes,
 // extents, strides and dtypes; data pointers are not part of the key).  With
 // autotuning on, the first call of a new key runs every applicable candidate
-// once to warm up and twice under HIP events on the caller's stream (so that
-// call synchronises the stream), keeps the fastest, and finishes with one
-// more launch of it, which produces the result.  Later calls of the key go
+// once to warm up, then times them round-robin under HIP events on the
+// caller's stream (three rounds; that call synchronises the stream), keeps
+// the fastest, and finishes with one more launch of it, which produces the
+// result.  Later calls of the key go
 // straight to the stored pick.  Calls made while the stream is capturing a
 // graph, and calls in plan-only mode, never tune.
 
@@ -439,27 +440,38 @@ static int tuned(const std::string& key, const int* cands, int nc, hipStream_t s
         e0 = e1 = nullptr;
         return run(-1);
     }
-    float best = 0.f;
-    int bp = PICK_NA;
-    for (int i = 0; i < nc; ++i) {
-        int rc = run(cands[i]);
+    // warm every applicable candidate once, then time them round-robin
+    // (three rounds, best of three per candidate) so that drift in clocks or
+    // memory state during tuning hits every candidate alike
+    constexpr int MAXC = 16, ROUNDS = 3;
+    int live[MAXC];
+    float tmin[MAXC];
+    int nl = 0;
+    for (int i = 0; i < nc && nl < MAXC; ++i) {
+        const int rc = run(cands[i]);
         if (rc == PICK_NA) continue;
         if (rc != TLIB_OK) return rc;
-        float tmin = 0.f;
-        for (int rep = 0; rep < 2; ++rep) {
+        live[nl] = cands[i];
+        tmin[nl++] = 0.f;
+    }
+    for (int round = 0; round < ROUNDS; ++round)
+        for (int i = 0; i < nl; ++i) {
             if (hipEventRecord(e0, s) != hipSuccess) return fail(TLIB_EHIP, "autotune: event record failed");
-            if ((rc = run(cands[i])) != TLIB_OK) return rc;
+            const int rc = run(live[i]);
+            if (rc != TLIB_OK) return rc;
             if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
                 return fail(TLIB_EHIP, "autotune: event wait failed");
             float ms = 0.f;
             hipEventElapsedTime(&ms, e0, e1);
-            if (rep == 0 || ms < tmin) tmin = ms;
+            if (round == 0 || ms < tmin[i]) tmin[i] = ms;
         }
-        if (bp == PICK_NA || tmin < best) {
-            best = tmin;
-            bp = cands[i];
+    int bp = PICK_NA;
+    float best = 0.f;
+    for (int i = 0; i < nl; ++i)
+        if (bp == PICK_NA || tmin[i] < best) {
+            best = tmin[i];
+            bp = live[i];
         }
-    }
     if (bp == PICK_NA) return run(-1);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
