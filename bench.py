@@ -334,6 +334,93 @@ def serve_bench(args):
     }
 
 
+def drivers_bench(args):
+    """The composite drivers on the order-4 160^4 workload: the Tucker chain
+    (TTM in modes 1..4 with 32x160 factors, FP32, and BF16 inputs with BF16
+    staging between steps) and 20 HOPM sweeps (FP32 TTVs, FP64 norms).
+    Algorithmic bytes count every kernel's inputs and outputs once."""
+    import torch
+
+    import paper_1711_10912_amd as T
+
+    dev = torch.device("cuda:0")
+    n, rank, rows = 160, 16, 32
+    g = torch.Generator(device=dev)
+    g.manual_seed(171110912 + 3)
+    # N(0,1) plus a rank-16 part with orthonormal factor columns and
+    # sigma_r = 1e5 * 0.8^(r-1); factors U_k (32 x 160) with orthonormal rows
+    # whose first 16 are the true factors
+    facs = [torch.linalg.qr(torch.randn(n, rows, generator=g, device=dev, dtype=torch.float64))[0]
+            for _ in range(4)]
+    sig = 1e5 * 0.8 ** torch.arange(rank, device=dev, dtype=torch.float64)
+    A = torch.randn((n,) * 4, generator=g, device=dev, dtype=torch.float32)
+    F = [f[:, :rank] for f in facs]
+    A += torch.einsum("r,ir,jr,kr,lr->ijkl", sig, *F).float()
+    Us = [f.T.contiguous().float() for f in facs]
+    A16 = A.to(torch.bfloat16)
+    Us16 = [u.to(torch.bfloat16) for u in Us]
+    torch.cuda.synchronize()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    def tucker_bytes(s_in, s_stage):
+        tot, shape = 0.0, [n] * 4
+        for k in range(4):
+            N = math.prod(shape)
+            out = N // shape[k] * rows
+            if k > 0 and s_stage != 4:
+                tot += N * (4 + s_stage)          # FP32 -> 16-bit staging pass
+            tot += N * (s_in if k == 0 else s_stage) + out * 4 + rows * n * s_in
+            shape[k] = rows
+        return tot
+
+    def tucker_flops():
+        tot, shape = 0.0, [n] * 4
+        for k in range(4):
+            tot += 2.0 * math.prod(shape) // shape[k] * rows * shape[k]
+            shape[k] = rows
+        return tot
+
+    reps = max(1, args.steps)
+    t32 = timed(lambda: T.tucker(A, Us), reps)
+    t16 = timed(lambda: T.tucker(A16, Us16, stage_dtype=torch.bfloat16), reps)
+    u0 = [torch.full((n,), 1.0 / math.sqrt(n), device=dev, dtype=torch.float32) for _ in range(4)]
+    iters = 20
+    t_h = timed(lambda: T.hopm(A, u0, iters), 1)
+    # per mode update: TTVs over the three other modes, highest first: A (n^4)
+    # -> n^3 -> n^2 -> n; one norm and one scale of an n-vector
+    per_update = 4.0 * (n ** 4 + n ** 3 + n ** 3 + n ** 2 + n ** 2 + n) + 4.0 * 3 * n
+    h_bytes = iters * 4 * per_update
+    lam, _ = T.hopm(A, u0, 2)
+    return {
+        "metric": METRIC,
+        "value": round(tucker_bytes(4, 4) / t32 / 1e9, 1),
+        "unit": "GB/s (Tucker chain FP32, algorithmic bytes / time)",
+        "n_gpus": 1, "steps": reps, "warmup": 1,
+        "ms_per_step": round(t32 * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32; bf16 inputs with f32 accumulation; f64 norms",
+        "data": "synthetic: 160^4 N(0,1) + rank-16 part (seeded)",
+        "config": {"workload": "Tucker chain 160^4 x_1..x_4 U_k (32x160), HOPM 20 sweeps"},
+        "tucker_f32": {"ms": round(t32 * 1e3, 3), "GB/s": round(tucker_bytes(4, 4) / t32 / 1e9, 1),
+                       "TFLOP/s": round(tucker_flops() / t32 / 1e12, 2),
+                       "roofline_frac": round(tucker_bytes(4, 4) / PEAK_HBM / t32, 4)},
+        "tucker_bf16": {"ms": round(t16 * 1e3, 3), "GB/s": round(tucker_bytes(2, 2) / t16 / 1e9, 1),
+                        "TFLOP/s": round(tucker_flops() / t16 / 1e12, 2),
+                        "roofline_frac": round(tucker_bytes(2, 2) / PEAK_HBM / t16, 4)},
+        "hopm_f32_20_sweeps": {"ms": round(t_h * 1e3, 2), "GB/s": round(h_bytes / t_h / 1e9, 1),
+                               "roofline_frac": round(h_bytes / PEAK_HBM / t_h, 4),
+                               "lambda_after_2_sweeps": [round(v, 2) for v in lam]},
+    }
+
+
 def run_step(cases, torch, ev):
     for i, c in enumerate(cases):
         if ev is not None:
@@ -406,7 +493,7 @@ def main():
     ap.add_argument("--autotune-save", default="", help="write the table after the first warmup step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cases-out", default="", help="write per-case timings (JSON lines) here")
-    ap.add_argument("--workload", default="sweep", choices=("sweep", "serve"),
+    ap.add_argument("--workload", default="sweep", choices=("sweep", "serve", "drivers"),
                     help="sweep: the order-p TTV/TTM sweep + TTT (default); serve: the served "
                          "mixed request stream (latency / req/s)")
     ap.add_argument("--requests", type=int, default=10000, help="serve: stream length")
@@ -435,6 +522,9 @@ def main():
 
     if args.workload == "serve":
         print(json.dumps(serve_bench(args)))
+        return
+    if args.workload == "drivers":
+        print(json.dumps(drivers_bench(args)))
         return
 
     dev = torch.device("cuda:0")
