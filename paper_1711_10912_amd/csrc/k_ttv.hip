@@ -134,10 +134,29 @@ __global__ __launch_bounds__(256) void ttv_slab_kernel(TtvParams P, int slabs, i
     const int64_t slab = int64_t(n_lo) * n_k;
 
     if (kc >= n_k) {
-        // whole slabs: one contiguous run of nS*slab elements
+        // whole slabs: one contiguous run of nS*slab elements, copied with
+        // 16-byte loads (four in flight per thread) when the run is aligned
         const TI* src = A + h0 * slab;
         const int total = int(int64_t(nS) * slab);
-        int i = tid;
+        int i0 = 0;
+        if ((reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+            typedef uint32_t q4_t __attribute__((ext_vector_type(4)));
+            constexpr int PER = 16 / int(sizeof(TI));
+            const int nq = total / PER;
+            const q4_t* sq = reinterpret_cast<const q4_t*>(src);
+            q4_t* lq = reinterpret_cast<q4_t*>(L);
+            int q = tid;
+            for (; q + 768 < nq; q += 1024) {
+                const q4_t v0 = sq[q], v1 = sq[q + 256], v2 = sq[q + 512], v3 = sq[q + 768];
+                lq[q] = v0;
+                lq[q + 256] = v1;
+                lq[q + 512] = v2;
+                lq[q + 768] = v3;
+            }
+            for (; q < nq; q += 256) lq[q] = sq[q];
+            i0 = nq * PER;
+        }
+        int i = i0 + tid;
         for (; i + 768 < total; i += 1024) {
             TI v0 = src[i], v1 = src[i + 256], v2 = src[i + 512], v3 = src[i + 768];
             L[i] = v0;
