@@ -77,8 +77,12 @@ template <typename TI> __device__ __forceinline__ typename Raw<TI>::type raw_loa
     else return *p;
 }
 
+// amdgpu_waves_per_eu(2): at least two waves per SIMD.  With it the compiler
+// keeps the accumulators in the unified VGPR file instead of splitting off
+// AGPRs, which measured 12-17 % faster for the FP64 tiles on MI355X and
+// neutral for the others.
 template <typename TI, int BM, int BN, int WGM, int WGN>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmParams P) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_kernel(GemmParams P) {
     using TA = typename AccOf<TI>::type;
     using RT = typename Raw<TI>::type;
     using acc_t = typename Mfma<TI>::acc_t;
