@@ -225,8 +225,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
         __syncthreads();
         if (k0 + BK < kend) fetch(slot ^ 1);
         slot ^= 1;
+        // the last slice of a K range stops at the first k-step that lies
+        // wholly past its end (those rows of the slice are zero)
+        const int klen = kend - k0;
 #pragma unroll
         for (int ks = 0; ks < BK; ks += KSTEP) {
+            if (ks >= klen) break;
             if constexpr (WIDE) {
                 u4_t a[FM], b[FN];
 #pragma unroll

@@ -60,15 +60,21 @@ __device__ __forceinline__ typename SMfma<TI>::acc_t smfma(typename SMfma<TI>::f
 __device__ __forceinline__ uint32_t raw16(const bf16_t* p) { return *reinterpret_cast<const uint16_t*>(p); }
 __device__ __forceinline__ uint32_t raw16(const f16_t* p) { return *reinterpret_cast<const uint16_t*>(p); }
 
+// Source of the fragment loads that fall outside the operand.
+__device__ __align__(16) double g_ttm_zero[2] = {0.0, 0.0};
+
 // The MFMA A-operand fragments of one column (base y) for KS k-steps: lane
 // (rl, kq) supplies k = s*KSTEP + kq (FP32/FP64) or k = s*32 + 8*kq + e, e < 8
-// (16-bit, packed in pairs).  Loads are unconditional from clamped in-range
-// addresses (k < K, and the caller clamps the column); out-of-range entries
-// are replaced by zero afterwards, so no load sits behind a branch.
+// (16-bit, packed in pairs).  Entries outside the operand (column not valid,
+// k >= K) load from a zero word instead: selecting the address rather than
+// the loaded value keeps every load unconditional, where a select after the
+// load lets the compiler sink the load into a branch and wait for it there
+// (and a wait on loads is also a wait on all of the wave's earlier stores).
 template <typename TI, int KS>
 __device__ __forceinline__ void load_frags(const TI* y, int64_t sk, int K, bool cv,
                                            int kq, typename SMfma<TI>::frag_t (&f)[KS]) {
     constexpr int KSTEP = SMfma<TI>::KSTEP;
+    const TI* zsrc = reinterpret_cast<const TI*>(g_ttm_zero);
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
         if constexpr (sizeof(TI) == 2) {
@@ -76,15 +82,14 @@ __device__ __forceinline__ void load_frags(const TI* y, int64_t sk, int K, bool 
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
                 const int k0 = s * 32 + 8 * kq + 2 * h;
-                const uint32_t lo = raw16(y + int64_t(min(k0, K - 1)) * sk);
-                const uint32_t hi = raw16(y + int64_t(min(k0 + 1, K - 1)) * sk);
-                w[h] = (cv && k0 < K ? lo : 0u) | ((cv && k0 + 1 < K ? hi : 0u) << 16);
+                const uint32_t lo = raw16(cv && k0 < K ? y + int64_t(k0) * sk : zsrc);
+                const uint32_t hi = raw16(cv && k0 + 1 < K ? y + int64_t(k0 + 1) * sk : zsrc);
+                w[h] = lo | (hi << 16);
             }
             f[s] = u4s_t{w[0], w[1], w[2], w[3]};
         } else {
             const int k = s * KSTEP + kq;
-            const TI v = y[int64_t(min(k, K - 1)) * sk];
-            f[s] = (cv && k < K) ? v : TI(0);
+            f[s] = *(cv && k < K ? y + int64_t(k) * sk : zsrc);
         }
     }
 }
