@@ -337,7 +337,9 @@ def serve_bench(args):
 def drivers_bench(args):
     """The composite drivers on the order-4 160^4 workload: the Tucker chain
     (TTM in modes 1..4 with 32x160 factors, FP32, and BF16 inputs with BF16
-    staging between steps) and 20 HOPM sweeps (FP32 TTVs, FP64 norms).
+    staging between steps), the one-pass multi-mode TTV for every excluded
+    mode (beside the chain of TTVs it replaces) and 20 HOPM sweeps built on it
+    (FP32 data, FP64 accumulation and norms).
     Algorithmic bytes count every kernel's inputs and outputs once."""
     import torch
 
@@ -392,11 +394,16 @@ def drivers_bench(args):
     t32 = timed(lambda: T.tucker(A, Us), reps)
     t16 = timed(lambda: T.tucker(A16, Us16, stage_dtype=torch.bfloat16), reps)
     u0 = [torch.full((n,), 1.0 / math.sqrt(n), device=dev, dtype=torch.float32) for _ in range(4)]
+    # the one-pass multi-mode TTV per excluded mode, against the chain of
+    # three TTVs it replaces; bytes: A once, three vectors and c
+    tv_bytes = 4.0 * n ** 4 + 4.0 * 4 * n
+    t_tv = [timed(lambda r=r: T.times_vectors(A, u0, r), reps) for r in range(1, 5)]
+    t_ch = [timed(lambda r=r: T.times_vectors_chain(A, u0, r), reps) for r in range(1, 5)]
     iters = 20
     t_h = timed(lambda: T.hopm(A, u0, iters), 1)
-    # per mode update: TTVs over the three other modes, highest first: A (n^4)
-    # -> n^3 -> n^2 -> n; one norm and one scale of an n-vector
-    per_update = 4.0 * (n ** 4 + n ** 3 + n ** 3 + n ** 2 + n ** 2 + n) + 4.0 * 3 * n
+    # per mode update: one pass over A (the multi-mode TTV), one norm and one
+    # scale of an n-vector
+    per_update = tv_bytes + 4.0 * 3 * n
     h_bytes = iters * 4 * per_update
     lam, _ = T.hopm(A, u0, 2)
     return {
@@ -408,13 +415,17 @@ def drivers_bench(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32; bf16 inputs with f32 accumulation; f64 norms",
         "data": "synthetic: 160^4 N(0,1) + rank-16 part (seeded)",
-        "config": {"workload": "Tucker chain 160^4 x_1..x_4 U_k (32x160), HOPM 20 sweeps"},
+        "config": {"workload": "Tucker chain 160^4 x_1..x_4 U_k (32x160), multi-mode TTV, HOPM 20 sweeps"},
         "tucker_f32": {"ms": round(t32 * 1e3, 3), "GB/s": round(tucker_bytes(4, 4) / t32 / 1e9, 1),
                        "TFLOP/s": round(tucker_flops() / t32 / 1e12, 2),
                        "roofline_frac": round(tucker_bytes(4, 4) / PEAK_HBM / t32, 4)},
         "tucker_bf16": {"ms": round(t16 * 1e3, 3), "GB/s": round(tucker_bytes(2, 2) / t16 / 1e9, 1),
                         "TFLOP/s": round(tucker_flops() / t16 / 1e12, 2),
                         "roofline_frac": round(tucker_bytes(2, 2) / PEAK_HBM / t16, 4)},
+        "times_vectors_f32": {"modes": [1, 2, 3, 4], "ms": [round(t * 1e3, 3) for t in t_tv],
+                              "GB/s": [round(tv_bytes / t / 1e9, 1) for t in t_tv],
+                              "roofline_frac": [round(tv_bytes / PEAK_HBM / t, 4) for t in t_tv],
+                              "chain_of_ttv_ms": [round(t * 1e3, 3) for t in t_ch]},
         "hopm_f32_20_sweeps": {"ms": round(t_h * 1e3, 2), "GB/s": round(h_bytes / t_h / 1e9, 1),
                                "roofline_frac": round(h_bytes / PEAK_HBM / t_h, 4),
                                "lambda_after_2_sweeps": [round(v, 2) for v in lam]},

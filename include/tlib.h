@@ -129,6 +129,21 @@ int tlib_scale(double alpha, const tlib_tensor* A, const tlib_tensor* C, void* s
  * Same dtype in and out; C must not overlap A. */
 int tlib_transpose(const tlib_tensor* A, const int32_t* tau, const tlib_tensor* C, void* stream);
 
+/* Multi-mode tensor-times-vector (Sec. 5.2 tensor_times_vectors, the product
+ * of the higher-order power method), in one pass over A:
+ *   c(i_r) = sum over all i_k, k != r, of A(i_1..i_p) * prod_{k != r} u_k(i_k).
+ * A: order p >= 2, any strides.  us: array of p descriptor pointers (host
+ * memory); us[r-1] is not read and may be NULL, every other us[k-1] is a
+ * vector of length n_k with A's dtype, any stride.  c: order 1, length n_r,
+ * FP64 for FP64 A and FP32 otherwise; it must not overlap A or a vector.
+ * Accumulates in FP64 in a fixed order (bitwise reproducible) and rounds once
+ * to c's dtype.  Uses the library's per-stream workspace (16 bytes per index
+ * of the modes outside the tile positions plus the partial sums); returns
+ * TLIB_ENOMEM if it cannot be allocated and TLIB_EINVAL if A has more than
+ * 2^31 tile positions or 2^30 row entries outside r. */
+int tlib_times_vectors(const tlib_tensor* A, const tlib_tensor* const* us, int32_t r,
+                       const tlib_tensor* c, void* stream);
+
 /* ---- Grouped launch of many small TTV / TTM requests ------------------------
  * A request is a TTV (op 0, B = the vector b) or a TTM (op 1, B = the matrix)
  * with the same argument rules as tlib_ttv / tlib_ttm.  tlib_batch_plan

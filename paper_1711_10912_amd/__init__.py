@@ -199,9 +199,29 @@ def transpose(A, tau: Sequence[int], out=None, layout=None):
     return out
 
 
-def times_vectors(A, us: Sequence, excluded: int):
-    """A multiplied with u_k in every mode k != excluded (1-based), highest
-    mode first, one TTV per mode (Sec. 5.2, tensor_times_vectors)."""
+def times_vectors(A, us: Sequence, excluded: int, out=None):
+    """c(i_r) = sum over every other index of A(i) * prod_{k != r} u_k(i_k),
+    r = excluded (1-based): A multiplied with u_k in every mode but r (Sec. 5.2,
+    tensor_times_vectors), in one pass over A with FP64 accumulation and one
+    rounding to c's dtype (FP64 for FP64 A, FP32 otherwise).  us[r-1] is not
+    read and may be None."""
+    p = A.dim()
+    if len(us) != p:
+        raise TlibError(_lib.EINVAL, "times_vectors: need %d vectors (got %d)" % (p, len(us)))
+    if out is None:
+        out = empty((A.shape[excluded - 1],), None, acc_dtype(A.dtype), A.device)
+    descs = [None if (k == excluded - 1 or us[k] is None) else _desc(us[k]) for k in range(p)]
+    arr = (ctypes.POINTER(_lib.TensorDesc) * p)(
+        *[ctypes.pointer(d) if d is not None else ctypes.POINTER(_lib.TensorDesc)() for d in descs])
+    _lib.check(_lib.lib().tlib_times_vectors(ctypes.byref(_desc(A)), arr, int(excluded), ctypes.byref(_desc(out)),
+                                             _stream(A)))
+    return out
+
+
+def times_vectors_chain(A, us: Sequence, excluded: int):
+    """The same product as a chain of mode-k TTVs, highest mode first (the
+    order the paper's tensor_times_vectors applies them), one launch per mode
+    with the intermediate tensors in between."""
     X = A
     for k in range(A.dim(), 0, -1):
         if k == excluded:

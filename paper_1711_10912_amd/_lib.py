@@ -17,7 +17,7 @@ MAX_ORDER = 16
 
 EXPORTS = (
     "tlib_ttv", "tlib_ttm", "tlib_ttt", "tlib_inner", "tlib_norm", "tlib_add", "tlib_scale",
-    "tlib_transpose", "tlib_batch_table_bytes", "tlib_batch_plan", "tlib_batch_run",
+    "tlib_transpose", "tlib_times_vectors", "tlib_batch_table_bytes", "tlib_batch_plan", "tlib_batch_run",
     "tlib_server_create", "tlib_server_submit", "tlib_server_drain", "tlib_server_stats",
     "tlib_server_result", "tlib_server_reset_stats", "tlib_server_destroy",
     "tlib_strides_from_layout", "tlib_last_error", "tlib_strerror", "tlib_set_plan_only",
@@ -83,6 +83,7 @@ def lib():
         L.tlib_add.argtypes = [ctypes.c_double, P, ctypes.c_double, P, P, vp]
         L.tlib_scale.argtypes = [ctypes.c_double, P, P, vp]
         L.tlib_transpose.argtypes = [P, i32p, P, vp]
+        L.tlib_times_vectors.argtypes = [P, ctypes.POINTER(P), ctypes.c_int32, P, vp]
         L.tlib_strides_from_layout.argtypes = [ctypes.c_int32, i64p, i32p, i64p]
         L.tlib_batch_table_bytes.argtypes = [ctypes.c_int32]
         L.tlib_batch_table_bytes.restype = ctypes.c_size_t
@@ -107,7 +108,7 @@ def lib():
         L.tlib_server_destroy.argtypes = [vp]
         L.tlib_server_destroy.restype = None
         for f in ("tlib_ttv", "tlib_ttm", "tlib_ttt", "tlib_inner", "tlib_norm", "tlib_add",
-                  "tlib_scale", "tlib_transpose", "tlib_strides_from_layout"):
+                  "tlib_scale", "tlib_transpose", "tlib_times_vectors", "tlib_strides_from_layout"):
             getattr(L, f).restype = ctypes.c_int
         L.tlib_last_error.restype = ctypes.c_char_p
         L.tlib_last_error.argtypes = []

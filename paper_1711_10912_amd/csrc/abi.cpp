@@ -1053,6 +1053,162 @@ int tlib_scale(double alpha, const tlib_tensor* A, const tlib_tensor* C, void* s
     return run_axpby(alpha, a, 0.0, nullptr, c, a.w, hipStream_t(stream), "scale");
 }
 
+// Multi-mode TTV in one pass (Sec. 5.2 tensor_times_vectors).  A's modes in
+// storage order: the position modes of a tile are the innermost ones (K1:
+// every mode up to and including r when few lo positions share an i_r; K2:
+// the longest prefix of the lo modes that fits a tile), the rest are rows.
+// Modes of extent 1 other than r only contribute u_k(0) to the weight and
+// join the hi group.
+int tlib_times_vectors(const tlib_tensor* A, const tlib_tensor* const* us, int32_t r, const tlib_tensor* C,
+                       void* stream) {
+    begin_call();
+    Ten a, c;
+    Ten u[MAXP];
+    int rc;
+    if ((rc = normalize(A, a, "A")) || (rc = normalize(C, c, "c"))) return rc;
+    if (a.p < 2) return fail(TLIB_EINVAL, "times_vectors: order of A must be >= 2 (got %d)", a.p);
+    if (r < 1 || r > a.p) return fail(TLIB_EMODE, "times_vectors: mode %d out of 1..%d", r, a.p);
+    if (!us) return fail(TLIB_EINVAL, "times_vectors: us is NULL");
+    const int ri = r - 1;
+    for (int k = 0; k < a.p; ++k) {
+        if (k == ri) continue;
+        char nm[16];
+        snprintf(nm, sizeof(nm), "u_%d", k + 1);
+        if ((rc = normalize(us[k], u[k], nm))) return rc;
+        if (u[k].p != 1 || u[k].n[0] != a.n[k])
+            return fail(TLIB_ESHAPE, "times_vectors: u_%d must be a vector of length %lld", k + 1,
+                        (long long)a.n[k]);
+        if (u[k].dtype != a.dtype) return fail(TLIB_EDTYPE, "times_vectors: u_%d must have A's dtype", k + 1);
+    }
+    if (c.p != 1 || c.n[0] != a.n[ri])
+        return fail(TLIB_ESHAPE, "times_vectors: c must be a vector of length n_%d = %lld", r, (long long)a.n[ri]);
+    if (c.dtype != acc_dtype(a.dtype))
+        return fail(TLIB_EDTYPE, "times_vectors: c must be %s", dname(acc_dtype(a.dtype)));
+    if (overlaps(c, a)) return fail(TLIB_EALIAS, "times_vectors: c overlaps A");
+    for (int k = 0; k < a.p; ++k)
+        if (k != ri && overlaps(c, u[k])) return fail(TLIB_EALIAS, "times_vectors: c overlaps u_%d", k + 1);
+
+    // storage order of the modes of extent > 1 and r
+    int ord[MAXP], no = 0, ones[MAXP], n1 = 0;
+    for (int k = 0; k < a.p; ++k) {
+        if (a.n[k] > 1 || k == ri) ord[no++] = k;
+        else ones[n1++] = k;
+    }
+    std::stable_sort(ord, ord + no, [&](int x, int y) { return a.w[x] < a.w[y]; });
+    int rho = 0;
+    while (ord[rho] != ri) ++rho;
+    int64_t n_lo = 1;
+    for (int j = 0; j < rho; ++j) n_lo *= a.n[ord[j]];
+
+    TvParams P{};
+    P.A = a.data;
+    P.n_r = a.n[ri];
+    auto add_mode = [&](TvModes& g, int k) {
+        g.n[g.nd] = a.n[k];
+        g.fd[g.nd] = make_fastdiv(uint32_t(std::min<int64_t>(a.n[k], 0x7fffffff)));
+        g.s[g.nd] = a.w[k];
+        g.u[g.nd] = k == ri ? nullptr : u[k].data;
+        g.us[g.nd] = k == ri ? 0 : u[k].w[0];
+        ++g.nd;
+    };
+    const bool k2 = n_lo >= 64;
+    int a_end;  // position modes are ord[0 .. a_end)
+    if (!k2) {
+        a_end = rho + 1;
+    } else {
+        a_end = 1;
+        int64_t pp = a.n[ord[0]];
+        while (a_end < rho && pp * a.n[ord[a_end]] <= TV_SLOTS) pp *= a.n[ord[a_end++]];
+    }
+    int64_t npos = 1;
+    for (int j = 0; j < a_end; ++j) {
+        add_mode(P.pos, ord[j]);
+        npos *= a.n[ord[j]];
+    }
+    int64_t n_out = 1, n_hi = 1;
+    if (k2)
+        for (int j = a_end; j < rho; ++j) {
+            add_mode(P.out, ord[j]);
+            n_out *= a.n[ord[j]];
+        }
+    for (int j = rho + 1; j < no; ++j) {
+        add_mode(P.hi, ord[j]);
+        n_hi *= a.n[ord[j]];
+    }
+    for (int j = 0; j < n1; ++j) add_mode(P.hi, ones[j]);
+    if (npos >= (int64_t(1) << 31) || n_out >= (int64_t(1) << 30) || a.n[ri] >= (int64_t(1) << 31))
+        return fail(TLIB_EINVAL, "times_vectors: A too large for one pass (%lld positions, %lld rows per i)",
+                    (long long)npos, (long long)n_out);
+    P.k2 = k2 ? 1 : 0;
+    P.npos = npos;
+    P.n_lo = k2 ? 1 : n_lo;
+    P.W = int32_t(std::min<int64_t>(npos, TV_SLOTS));
+    P.G = npos <= TV_SLOTS ? int32_t(TV_SLOTS / npos) : 1;
+    P.nfc = int32_t((npos + P.W - 1) / P.W);
+    P.nloc = k2 ? 1 : int32_t(P.W / n_lo + 2);
+    P.n_out = n_out;
+    P.n_hi = n_hi;
+    P.fd_out = make_fastdiv(uint32_t(n_out));
+    P.s_r = a.w[ri];
+    // dense row groups: the offset of row (o, h) is o * s_o + h * s_h
+    {
+        auto linear = [](const TvModes& g, int64_t& s0) {
+            s0 = 0;
+            int64_t want = -1;
+            for (int j = 0; j < g.nd; ++j) {
+                if (g.n[j] == 1) continue;
+                if (want < 0) s0 = g.s[j];
+                else if (g.s[j] != want) return false;
+                want = g.s[j] * g.n[j];
+            }
+            return true;
+        };
+        // (one weight per row when the row count stays modest, <= 2^26)
+        P.lin = (linear(P.out, P.s_o) && linear(P.hi, P.s_h) && n_out * n_hi <= (int64_t(1) << 26)) ? 1 : 0;
+    }
+    // rows per i_r: n_out * n_hi, split into HC ranges so that the grid holds
+    // about 2048 workgroups; a range is at most 2^30 rows
+    const int64_t rows = n_out * n_hi;
+    const int64_t items = (k2 ? P.n_r : 1) * int64_t(P.nfc);
+    int64_t hc = std::max<int64_t>(1, std::min<int64_t>((2048 + items - 1) / items, (rows + P.G - 1) / P.G));
+    int64_t tlen = (rows + hc - 1) / hc;
+    tlen = std::min<int64_t>(tlen, int64_t(1) << 30);
+    hc = (rows + tlen - 1) / tlen;
+    if (items * hc >= (int64_t(1) << 31)) return fail(TLIB_EINVAL, "times_vectors: grid too large");
+    P.HC = int32_t(hc);
+    P.hc_len = tlen;
+    // 16-byte loads: dense positions (offset = index), a multiple of the
+    // vector in every row offset and in the tile width, aligned base
+    const int esz = esize(a.dtype), vlen = 16 / esz;
+    bool vec = (uintptr_t(a.data) % 16) == 0 && npos % vlen == 0;
+    {
+        int64_t want = 1;
+        for (int j = 0; j < P.pos.nd; ++j) {
+            vec = vec && P.pos.s[j] == want;
+            want *= P.pos.n[j];
+        }
+        for (int j = 0; j < P.out.nd; ++j) vec = vec && (P.out.n[j] == 1 || P.out.s[j] % vlen == 0);
+        for (int j = 0; j < P.hi.nd; ++j) vec = vec && (P.hi.n[j] == 1 || P.hi.s[j] % vlen == 0);
+        if (k2) vec = vec && (P.n_r == 1 || P.s_r % vlen == 0);
+    }
+    const int64_t ntab = P.lin ? n_out * n_hi : n_out + n_hi;
+    const int64_t nparts = k2 ? P.n_r * P.HC * P.nfc : int64_t(P.HC) * P.nfc * P.nloc;
+    const size_t wsb = size_t(ntab) * 16 + size_t(nparts) * 8;
+    plan_note("times_vectors %s dtype=%s mode=%d positions=%lld W=%d G=%d chunks=%d rows=%lld (out %lld x hi %lld) "
+              "HC=%d vec=%d lin=%d grid=%lld",
+              k2 ? "k2" : "k1", dname(a.dtype), r, (long long)npos, P.W, P.G, P.nfc, (long long)rows,
+              (long long)n_out, (long long)n_hi, P.HC, vec ? 1 : 0, P.lin, (long long)(items * hc));
+    if (g_plan_only) return TLIB_OK;
+    hipStream_t s = hipStream_t(stream);
+    char* ws = static_cast<char*>(workspace(s, wsb));
+    if (!ws) return fail(TLIB_ENOMEM, "times_vectors: workspace of %zu bytes", wsb);
+    P.tabw = reinterpret_cast<double*>(ws);
+    P.tabo = reinterpret_cast<int64_t*>(ws + ntab * 8);
+    P.part = reinterpret_cast<double*>(ws + ntab * 16);
+    rc = launch_tv(a.dtype, P, c.data, c.w[0], vec, s);
+    return rc ? fail(rc, "times_vectors: launch failed") : TLIB_OK;
+}
+
 int tlib_transpose(const tlib_tensor* A, const int32_t* tau, const tlib_tensor* C, void* stream) {
     begin_call();
     Ten a, c;

@@ -95,6 +95,48 @@ struct GemmParams {
     void* part;              // split-K partials [ksplit][M][N] (accumulator type)
 };
 
+// Multi-mode TTV (one pass over A).  A group of modes in storage order,
+// fastest first: extents, A strides, and the vector of each mode (nullptr for
+// the excluded mode r).
+struct TvModes {
+    int nd = 0;
+    int64_t n[MAXP] = {};
+    FastDiv fd[MAXP];
+    int64_t s[MAXP] = {};
+    const void* u[MAXP] = {};
+    int64_t us[MAXP] = {};
+};
+
+constexpr int TV_SLOTS = 2048;  // positions per tile (8 per thread)
+
+// pos: the tile's position modes (K1: ending with r); out: the lo modes
+// between the positions and r (K2 only); hi: the modes after r.  A block
+// (ib, fc, hc) streams rows t = o + n_out * (h - h0), o < n_out, h in
+// [h0, h0 + hc_len), G rows of W positions per tile.
+struct TvParams {
+    const void* A = nullptr;
+    TvModes pos, out, hi;
+    int64_t npos = 1;    // positions (product of pos extents), < 2^31
+    int64_t n_lo = 1;    // K1: positions per value of i_r
+    int64_t n_r = 1;
+    int32_t W = 1;       // positions per tile row
+    int32_t G = 1;       // rows per tile (G * W <= TV_SLOTS)
+    int32_t nfc = 1;     // position chunks
+    int32_t nloc = 1;    // K1: partial slots per chunk
+    int32_t HC = 1;      // row chunks
+    int32_t k2 = 0;
+    int64_t n_out = 1, n_hi = 1;
+    FastDiv fd_out;
+    int64_t hc_len = 1;  // slabs per row chunk (n_out * hc_len < 2^31)
+    int64_t s_r = 0;     // K2: A stride of mode r
+    int32_t lin = 0;     // row offset = o * s_o + h * s_h (no offset table), and
+                         // one weight per row t in tabw (n_out * n_hi entries)
+    int64_t s_o = 0, s_h = 0;
+    double* tabw = nullptr;   // lin: row weights [n_out * n_hi]; else weights [n_out + n_hi]
+    int64_t* tabo = nullptr;  // row offsets [n_out + n_hi] (not lin)
+    double* part = nullptr;   // partial sums
+};
+
 // Streaming TTM with a short contraction: X = B (M x K, strides sXm, sXk),
 // Y = A (columns nu over gn, stride sYk along k), C(j, nu) at j*sCm + gn.s1.
 struct TtmParams {
@@ -168,6 +210,8 @@ int launch_ttv_slab(int dtype, const TtvParams& p, int slabs, int kc, hipStream_
 int launch_ttv_generic(int dtype, const TtvParams& p, const GDims& out, hipStream_t s);
 
 int launch_gemm(int dtype, int tile, const GemmParams& p, hipStream_t s);
+// prep + main + finish kernels of the one-pass multi-mode TTV; vec: 16-byte loads
+int launch_tv(int dtype, const TvParams& P, void* c, int64_t cs, bool vec, hipStream_t s);
 // fm: row blocks (1, 4 or 16); ks: k-steps from ttm_stream_ks (0 = unsupported)
 int launch_ttm_stream(int dtype, const TtmParams& p, int fm, int ks, bool trans, int grid, hipStream_t s);
 int ttm_stream_ks(int dtype, int k);

@@ -203,3 +203,39 @@ def test_autotune_controls(tmp_path):
     finally:
         T.autotune_clear()
         T.set_autotune(prev)
+
+
+def _tv(A, us, r, c):
+    arr = (ctypes.POINTER(_lib.TensorDesc) * len(us))(
+        *[ctypes.pointer(u) if u is not None else ctypes.POINTER(_lib.TensorDesc)() for u in us])
+    return _lib.lib().tlib_times_vectors(ctypes.byref(A), arr, r, ctypes.byref(c), None)
+
+
+def test_times_vectors_plans_and_errors():
+    with Plan():
+        n = 160
+        A = _d((n,) * 4, _lib.F32)
+        us = [_d((n,), _lib.F32, ptr=FAKE * (2 + k)) for k in range(4)]
+        c = _d((n,), _lib.F32, ptr=FAKE * 9)
+        # r = 1 is the stride-1 mode: its index runs over the tile positions
+        assert _tv(A, us, 1, c) == 0 and _plan().startswith("times_vectors k1") and "vec=1" in _plan()
+        # r = 4: one i_r per workgroup, every element of A read once
+        assert _tv(A, us, 4, c) == 0 and _plan().startswith("times_vectors k2") and "out 25600 x hi 1" in _plan()
+        # u_r is not read and may be NULL
+        assert _tv(A, us[:1] + [None] + us[2:], 2, c) == 0
+        # a view with gaps in the position modes takes the scalar path
+        Ag = _d((n, n, n, n), _lib.F32, strides=(2, 2 * n, 2 * n * n, 2 * n ** 3))
+        assert _tv(Ag, us, 2, c) == 0 and "vec=0" in _plan()
+        # errors
+        assert _tv(A, us, 0, c) == _lib.EMODE
+        assert _tv(A, us, 5, c) == _lib.EMODE
+        assert _tv(A, us[:2] + [_d((n + 1,), _lib.F32, ptr=FAKE * 4)] + us[3:], 1, c) == _lib.ESHAPE
+        assert _tv(A, us, 1, _d((n + 1,), _lib.F32, ptr=FAKE * 9)) == _lib.ESHAPE
+        assert _tv(A, us, 1, _d((n,), _lib.F64, ptr=FAKE * 9)) == _lib.EDTYPE
+        assert _tv(A, us[:1] + [_d((n,), _lib.F64, ptr=FAKE * 3)] + us[2:], 1, c) == _lib.EDTYPE
+        assert _tv(A, us, 1, _d((n,), _lib.F32, ptr=FAKE + 64)) == _lib.EALIAS
+        assert _tv(_d((n,), _lib.F32), us[:1], 1, c) == _lib.EINVAL
+        # 16-bit inputs give an FP32 result
+        Ab = _d((n,) * 4, _lib.BF16)
+        ub = [_d((n,), _lib.BF16, ptr=FAKE * (2 + k)) for k in range(4)]
+        assert _tv(Ab, ub, 3, c) == 0
