@@ -538,6 +538,18 @@ static int run_gemm(int dtype, const void* X, const void* Y, void* C, Dim* dm, i
         }
         P.x_kfast = ndk > 0 && (ndm == 0 || minstride(dk, ndk, 0) < minstride(dm, ndm, 0));
         P.y_kfast = ndk > 0 && (ndn == 0 || minstride(dk, ndk, 1) < minstride(dn, ndn, 0));
+        {
+            // Y as vectors along N: FP32/FP64, N's first dim of unit stride in
+            // Y, K one dim; 16-byte vectors when K's stride keeps them
+            // aligned, else 8-byte ones (FP32) when it keeps those aligned
+            P.syk = ndk == 1 ? dk[0].s[1] : 0;
+            P.y_vec = 0;
+            if ((dtype == TLIB_F32 || dtype == TLIB_F64) && !P.y_kfast && ndk == 1 && ndn >= 1 && dn[0].s[0] == 1) {
+                const int v16 = 16 / esize(dtype);
+                if (P.syk % v16 == 0 && (uintptr_t(Y) % 16) == 0) P.y_vec = v16;
+                else if (dtype == TLIB_F32 && P.syk % 2 == 0 && (uintptr_t(Y) % 8) == 0) P.y_vec = 2;
+            }
+        }
         // FP64 accumulators are twice as wide: keep a wave's tile at 64x32 so
         // that two waves fit per SIMD.
         const bool wide_acc = dtype == TLIB_F64;
@@ -573,9 +585,9 @@ static int run_gemm(int dtype, const void* X, const void* Y, void* C, Dim* dm, i
                                         size_t(esize(acc_dtype(dtype)))
                                   : 0;
         plan_note("%s gemm dtype=%s M=%lld N=%lld K=%lld dims=(%d,%d,%d) tile=%dx%d kfast=(%d,%d) "
-                  "cvec=%d ksplit=%d tiles=%lld",
+                  "cvec=%d yvec=%d ksplit=%d tiles=%lld",
                   op, dname(dtype), (long long)M, (long long)N, (long long)K, ndm, ndn, ndk, ts.bm,
-                  ts.bn, P.x_kfast, P.y_kfast, P.c_vec, P.ksplit, (long long)nt);
+                  ts.bn, P.x_kfast, P.y_kfast, P.c_vec, P.y_vec, P.ksplit, (long long)nt);
         if (g_plan_only) return TLIB_OK;
         if (P.ksplit > 1) {
             P.part = workspace(s, wsb);

@@ -93,6 +93,8 @@ struct GemmParams {
     int32_t tiles_m, tiles_n;
     int32_t ksplit, kchunk;  // split-K: each z-slice handles kchunk of K
     void* part;              // split-K partials [ksplit][M][N] (accumulator type)
+    int32_t y_vec;           // > 0: Y loaded as vectors of y_vec elements along N (K one dim, stride syk)
+    int64_t syk;
 };
 
 // Multi-mode TTV (one pass over A).  A group of modes in storage order,

@@ -27,6 +27,9 @@ typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
 typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
 
+// Source of the loads of vector slots that fall outside Y.
+__device__ __align__(16) double g_gemm_zero[2] = {0.0, 0.0};
+
 template <typename TI> struct Mfma;
 
 // BK: depth of one K slice staged through LDS (several MFMA k-steps), chosen
@@ -81,7 +84,12 @@ template <typename TI> __device__ __forceinline__ typename Raw<TI>::type raw_loa
 // keeps the accumulators in the unified VGPR file instead of splitting off
 // AGPRs, which measured 12-17 % faster for the FP64 tiles on MI355X and
 // neutral for the others.
-template <typename TI, int BM, int BN, int WGM, int WGN>
+// YW > 0: Y's slice loaded as vectors of YW elements along N (16 or 8
+// bytes).  Each thread owns YW consecutive columns for the whole K walk (their offset is decoded once) and
+// every RS-th row of each slice; a wave in which some thread's columns are not
+// consecutive in memory (the end of a run of N's first dim, or past N) loads
+// its columns one by one.
+template <typename TI, int BM, int BN, int WGM, int WGN, int YW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_kernel(GemmParams P) {
     using TA = typename AccOf<TI>::type;
     using RT = typename Raw<TI>::type;
@@ -101,6 +109,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
     constexpr int EX = BM * BK / 256;  // X elements per thread per K slice
     constexpr int EY = BN * BK / 256;
     static_assert(EX >= 1 && EY >= 1, "tile too small");
+    constexpr bool YV = YW > 0;
+    constexpr int VY = YV ? YW : 1;
+    constexpr int CG = BN / VY;                   // column groups of a Y slice
+    constexpr int RS = YV ? 256 / CG : 1;         // rows of the slice per pass
+    constexpr int EYV = YV ? BK / RS : 1;         // vectors per thread per slice
+    static_assert(!YV || (sizeof(TI) >= 4 && 256 % CG == 0 && BK % RS == 0 && EYV >= 1), "vector Y slice");
+    using YE = typename std::conditional<(sizeof(TI) >= 4), TI, float>::type;
+    typedef YE yv_t __attribute__((ext_vector_type(VY)));
 
     // The X/Y slices and, after the K loop, the epilogue's staging rows share
     // one LDS buffer.
@@ -172,7 +188,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
         else { nn = e % BN; kk = e / BN; }
     };
 
-    RT xr[EX], yr[EY];
+    RT xr[EX], yr[YV ? 1 : EY];
+    yv_t yvr[EYV];
+    // YV: this thread's column group and first row, the group's offset and
+    // whether every thread of the wave has VY consecutive, aligned columns
+    const int ycg = tid % CG, yrow = tid / CG;
+    int64_t ycv = 0;
+    bool wvec = false;
+    int k0n = 0;  // first k of the slice being fetched
+    const TI* zsrc = reinterpret_cast<const TI*>(g_gemm_zero);
     auto fetch = [&](int slot) {
 #pragma unroll
         for (int j = 0; j < EX; ++j) {
@@ -181,12 +205,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
             const int64_t a = xrow[mm], b = kx[slot][kk];
             xr[j] = (a >= 0 && b >= 0) ? raw_load(X + a + b) : RT(0);
         }
+        if constexpr (YV) {
+            // the choice is per wave (wvec is uniform), so only one of the two
+            // load sequences runs and no load waits for the other's registers
+            if (wvec) {
 #pragma unroll
-        for (int j = 0; j < EY; ++j) {
-            int nn, kk;
-            yslot(j, nn, kk);
-            const int64_t a = ycol[nn], b = ky[slot][kk];
-            yr[j] = (a >= 0 && b >= 0) ? raw_load(Y + a + b) : RT(0);
+                for (int j = 0; j < EYV; ++j) {
+                    const int k = k0n + yrow + RS * j;
+                    yvr[j] = *reinterpret_cast<const yv_t*>(k < kend ? Y + (ycv + int64_t(k) * P.syk) : zsrc);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < EYV; ++j) {
+                    const int k = k0n + yrow + RS * j;
+#pragma unroll
+                    for (int e = 0; e < VY; ++e) {
+                        const int64_t a = ycol[ycg * VY + e];
+                        yvr[j][e] = *((a >= 0 && k < kend) ? Y + (a + int64_t(k) * P.syk) : zsrc);
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < EY; ++j) {
+                int nn, kk;
+                yslot(j, nn, kk);
+                const int64_t a = ycol[nn], b = ky[slot][kk];
+                yr[j] = (a >= 0 && b >= 0) ? raw_load(Y + a + b) : RT(0);
+            }
         }
     };
     auto stash = [&]() {
@@ -197,12 +243,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
             if constexpr (WIDE) Xs[mm * PX + kk] = xr[j];
             else Xs[kk * PX + mm] = xr[j];
         }
+        if constexpr (YV) {
 #pragma unroll
-        for (int j = 0; j < EY; ++j) {
-            int nn, kk;
-            yslot(j, nn, kk);
-            if constexpr (WIDE) Ys[nn * PY + kk] = yr[j];
-            else Ys[kk * PY + nn] = yr[j];
+            for (int j = 0; j < EYV; ++j) *reinterpret_cast<yv_t*>(&Ys[(yrow + RS * j) * PY + ycg * VY]) = yvr[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < EY; ++j) {
+                int nn, kk;
+                yslot(j, nn, kk);
+                if constexpr (WIDE) Ys[nn * PY + kk] = yr[j];
+                else Ys[kk * PY + nn] = yr[j];
+            }
         }
     };
 
@@ -217,12 +268,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
 
     ktable(kbeg, 0);
     __syncthreads();
+    if constexpr (YV) {
+        ycv = ycol[ycg * VY];
+        bool ok = ycv >= 0 && (ycv % VY) == 0;
+#pragma unroll
+        for (int e = 1; e < VY; ++e) ok = ok && ycol[ycg * VY + e] == ycv + e;
+        wvec = __ballot(!ok) == 0;
+    }
+    k0n = kbeg;
     if (kbeg < kend) fetch(0);
     int slot = 0;
     for (int k0 = kbeg; k0 < kend; k0 += BK) {
         stash();
         if (k0 + BK < kend) ktable(k0 + BK, slot ^ 1);
         __syncthreads();
+        k0n = k0 + BK;
         if (k0 + BK < kend) fetch(slot ^ 1);
         slot ^= 1;
         // the last slice of a K range stops at the first k-step that lies
@@ -359,7 +419,17 @@ template <typename TI, int BM, int BN, int WGM, int WGN>
 static int gemm_launch(const GemmParams& p, hipStream_t s) {
     using TA = typename AccOf<TI>::type;
     const unsigned tiles = unsigned(p.tiles_m) * unsigned(p.tiles_n);
-    hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN>), dim3(tiles, unsigned(p.ksplit)), dim3(256), 0, s, p);
+    const dim3 grid(tiles, unsigned(p.ksplit));
+    if constexpr (sizeof(TI) == 8) {
+        if (p.y_vec == 2) hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 2>), grid, dim3(256), 0, s, p);
+        else hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 0>), grid, dim3(256), 0, s, p);
+    } else if constexpr (sizeof(TI) == 4) {
+        if (p.y_vec == 4) hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 4>), grid, dim3(256), 0, s, p);
+        else if (p.y_vec == 2) hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 2>), grid, dim3(256), 0, s, p);
+        else hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 0>), grid, dim3(256), 0, s, p);
+    } else {
+        hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 0>), grid, dim3(256), 0, s, p);
+    }
     if (hipGetLastError() != hipSuccess) return TLIB_EHIP;
     if (p.ksplit > 1) {
         const int64_t MN = int64_t(p.M) * p.N;
