@@ -92,6 +92,21 @@ int tlib_ttv(const tlib_tensor* A, const tlib_tensor* b, int32_t m,
 int tlib_ttm(const tlib_tensor* A, const tlib_tensor* B, int32_t m,
              const tlib_tensor* C, void* stream);
 
+/* Two mode products in one pass, C = (A x_a Ua) x_b Ub (Sec. 5.2 Eq. ttm in
+ * modes a and b, a != b; one step pair of tensor_times_matrices, as in the
+ * Tucker chain):
+ *   C(.., j_a, .., j_b, ..) = sum_{i_a, i_b} Ua(j_a, i_a) Ub(j_b, i_b) A(.., i_a, .., i_b, ..).
+ * A: order p >= 2, FP64 or FP32, any strides.  Ua: shape (n'_a, n_a), Ub:
+ * shape (n'_b, n_b), A's dtype, any strides.  C: extents of A with n_a, n_b
+ * replaced by n'_a, n'_b, A's dtype, any injective strides, no overlap with
+ * an input.  Without writing A x_a Ua when n'_a, n'_b <= 32 and n_a, n_b <=
+ * 256 (the result is the same product summed in another order); otherwise
+ * two TTMs through an intermediate held in the library's per-stream
+ * workspace (TLIB_ENOMEM if it cannot be allocated).  16-bit inputs:
+ * TLIB_EDTYPE (use two tlib_ttm calls). */
+int tlib_ttm2(const tlib_tensor* A, const tlib_tensor* Ua, int32_t a, const tlib_tensor* Ub,
+              int32_t b, const tlib_tensor* C, void* stream);
+
 /* (q, phi, psi)-mode tensor-times-tensor, Sec. 5.2 Eq. ttt and ttt_indices.
  * A has order q+r, B order q+s (r, s, q >= 0, q+r > 0, q+s > 0); phi (length
  * q+r) and psi (length q+s) are 1-based permutations.  C has order r+s with

@@ -130,6 +130,22 @@ def ttt_shape(na, nb, q, phi, psi) -> tuple:
     return tuple(na[phi[k] - 1] for k in range(r)) + tuple(nb[psi[k] - 1] for k in range(s))
 
 
+def ttm2(A, Ua, a: int, Ub, b: int, out=None, layout=None):
+    """C = (A x_a Ua) x_b Ub in one pass (Sec. 5.2 Eq. ttm in two modes): the
+    intermediate A x_a Ua is not written when the factors have at most 32
+    rows.  FP32/FP64.  The result keeps A's layout by default."""
+    if out is None:
+        shape = list(A.shape)
+        shape[a - 1] = Ua.shape[0]
+        shape[b - 1] = Ub.shape[0]
+        if layout is None:
+            layout = layout_of(A)
+        out = empty(tuple(shape), layout, A.dtype, A.device)
+    _lib.check(_lib.lib().tlib_ttm2(ctypes.byref(_desc(A)), ctypes.byref(_desc(Ua)), int(a), ctypes.byref(_desc(Ub)),
+                                    int(b), ctypes.byref(_desc(out)), _stream(A)))
+    return out
+
+
 def ttt(A, B, q: int, phi: Sequence[int], psi: Sequence[int], out=None, layout=None):
     """(q, phi, psi)-mode tensor-times-tensor (Sec. 5.2 Eq. ttt, ttt_indices)."""
     if out is None:

@@ -235,11 +235,11 @@ std::mutex g_ws_mu;
 std::map<std::pair<int, hipStream_t>, WsEntry> g_ws;
 }  // namespace
 
-void* workspace(hipStream_t s, size_t bytes) {
+static void* workspace_slot(hipStream_t s, size_t bytes, int slot) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return nullptr;
     std::lock_guard<std::mutex> lk(g_ws_mu);
-    WsEntry& e = g_ws[{dev, s}];
+    WsEntry& e = g_ws[{dev * 2 + slot, s}];
     if (e.bytes >= bytes && e.ptr) return e.ptr;
     if (e.ptr) {
         // kernels already queued on this stream may still read the old buffer
@@ -258,6 +258,9 @@ void* workspace(hipStream_t s, size_t bytes) {
     e.bytes = want;
     return p;
 }
+
+void* workspace(hipStream_t s, size_t bytes) { return workspace_slot(s, bytes, 0); }
+void* workspace2(hipStream_t s, size_t bytes) { return workspace_slot(s, bytes, 1); }
 
 // ------------------------------------------------------------------ TTV planning
 
@@ -932,6 +935,119 @@ int tlib_ttm(const tlib_tensor* A, const tlib_tensor* B, int32_t m, const tlib_t
     key_ten(key, c);
     return tuned(key, cands, int(sizeof(cands) / sizeof(cands[0])), hipStream_t(stream),
                  [&](int pick) { return ttm_dispatch(a, bm, mi, c, pick, stream); });
+}
+
+// Two mode products C = (A x_a Ua) x_b Ub in one pass (Sec. 5.2 Eq. ttm
+// twice; a step pair of tensor_times_matrices).  The fused kernel serves
+// FP32/FP64 with factor rows <= 32, contracted extents <= 256 and columns that
+// collapse to a few (extent, stride) pairs; otherwise the two products run as
+// TTMs through an intermediate in the stream's second workspace.
+int tlib_ttm2(const tlib_tensor* A, const tlib_tensor* Ua, int32_t ma, const tlib_tensor* Ub, int32_t mb,
+              const tlib_tensor* C, void* stream) {
+    begin_call();
+    Ten a, ua, ub, c;
+    int rc;
+    if ((rc = normalize(A, a, "A")) || (rc = normalize(Ua, ua, "Ua")) || (rc = normalize(Ub, ub, "Ub")) ||
+        (rc = normalize(C, c, "C")))
+        return rc;
+    if (a.p < 2) return fail(TLIB_EINVAL, "ttm2: order of A must be >= 2 (got %d)", a.p);
+    if (ma < 1 || ma > a.p || mb < 1 || mb > a.p || ma == mb)
+        return fail(TLIB_EMODE, "ttm2: modes %d, %d must be distinct and in 1..%d", ma, mb, a.p);
+    const int ia = ma - 1, ib = mb - 1;
+    if (ua.p != 2 || ua.n[1] != a.n[ia])
+        return fail(TLIB_ESHAPE, "ttm2: Ua must have shape (n', n_%d = %lld)", ma, (long long)a.n[ia]);
+    if (ub.p != 2 || ub.n[1] != a.n[ib])
+        return fail(TLIB_ESHAPE, "ttm2: Ub must have shape (n', n_%d = %lld)", mb, (long long)a.n[ib]);
+    if (c.p != a.p) return fail(TLIB_ESHAPE, "ttm2: C must have order %d", a.p);
+    for (int r = 0; r < a.p; ++r) {
+        const int64_t want = r == ia ? ua.n[0] : r == ib ? ub.n[0] : a.n[r];
+        if (c.n[r] != want) return fail(TLIB_ESHAPE, "ttm2: extent %d of C must be %lld", r + 1, (long long)want);
+    }
+    if (a.dtype != TLIB_F64 && a.dtype != TLIB_F32)
+        return fail(TLIB_EDTYPE, "ttm2: A must be FP64 or FP32 (16-bit inputs: two tlib_ttm calls)");
+    if (ua.dtype != a.dtype || ub.dtype != a.dtype || c.dtype != a.dtype)
+        return fail(TLIB_EDTYPE, "ttm2: Ua, Ub and C must have A's dtype");
+    if ((rc = check_output(c, "C"))) return rc;
+    if (overlaps(c, a) || overlaps(c, ua) || overlaps(c, ub)) return fail(TLIB_EALIAS, "ttm2: C overlaps an input");
+    hipStream_t s = hipStream_t(stream);
+
+    // f: the contracted mode with the smaller stride in A
+    const bool a_fast = a.w[ia] <= a.w[ib];
+    const int fi = a_fast ? ia : ib, gi = a_fast ? ib : ia;
+    const Ten& uf = a_fast ? ua : ub;
+    const Ten& ug = a_fast ? ub : ua;
+    Ttm2Params P{};
+    P.A = a.data;
+    P.Uf = uf.data;
+    P.Ug = ug.data;
+    P.C = c.data;
+    P.n_f = int32_t(std::min<int64_t>(a.n[fi], 1 << 30));
+    P.n_g = int32_t(std::min<int64_t>(a.n[gi], 1 << 30));
+    P.m_f = int32_t(std::min<int64_t>(uf.n[0], 1 << 30));
+    P.m_g = int32_t(std::min<int64_t>(ug.n[0], 1 << 30));
+    P.s_f = a.w[fi];
+    P.s_g = a.w[gi];
+    P.sUf0 = uf.w[0];
+    P.sUf1 = uf.w[1];
+    P.sUg0 = ug.w[0];
+    P.sUg1 = ug.w[1];
+    P.sC_f = c.w[fi];
+    P.sC_g = c.w[gi];
+    Dim dc[MAXP];
+    int ndc = 0;
+    int64_t ncol = 1;
+    for (int r = 0; r < a.p; ++r)
+        if (r != fi && r != gi) {
+            dc[ndc++] = {a.n[r], {a.w[r], c.w[r], 0}};
+            ncol *= a.n[r];
+        }
+    ndc = coalesce(dc, ndc, 2, 0);
+    P.ncol = ncol;
+    // slab copy with 16-byte loads: the columns' first dim has unit stride
+    // in A and whole tiles of 16, and every A offset of a tile start is a
+    // multiple of the vector
+    const int va = 16 / esize(a.dtype);
+    bool vec = ndc >= 1 && dc[0].s[0] == 1 && dc[0].n % 16 == 0 && (uintptr_t(a.data) % 16) == 0 &&
+               P.s_f % va == 0 && P.s_g % va == 0 && a.n[fi] <= ttm2_vec_rows(a.dtype);
+    for (int i = 1; i < ndc; ++i) vec = vec && dc[i].s[0] % va == 0;
+    int lds = ttm2_lds_bytes(a.dtype, P.m_f, P.n_f, P.n_g, vec);
+    if (vec && lds > 73728) {
+        vec = false;
+        lds = ttm2_lds_bytes(a.dtype, P.m_f, P.n_f, P.n_g, false);
+    }
+    // a grid of fewer than 256 column tiles leaves most of the chip idle: a
+    // large tensor with few columns takes the two TTMs
+    const bool fused = uf.n[0] <= 32 && ug.n[0] <= 32 && a.n[fi] <= 256 && a.n[gi] <= 256 &&
+                       lds <= (vec ? 73728 : 65536) && ncol < (int64_t(1) << 31) &&
+                       (ncol >= 256 * 16 || a.numel() <= (int64_t(1) << 22)) && fill_grp(P.gc, dc, ndc, 0, 1);
+    if (fused) {
+        plan_note("ttm2 fused dtype=%s f=%d g=%d n=(%d,%d) m=(%d,%d) columns=%lld dims=%d vec=%d lds=%d grid=%lld",
+                  dname(a.dtype), fi + 1, gi + 1, P.n_f, P.n_g, P.m_f, P.m_g, (long long)ncol, ndc, vec ? 1 : 0, lds,
+                  (long long)((ncol + 15) / 16));
+        if (g_plan_only) return TLIB_OK;
+        rc = launch_ttm2(a.dtype, P, vec, s);
+        return rc ? fail(rc, "ttm2: launch failed") : TLIB_OK;
+    }
+    // two TTMs: T = A x_a Ua in A's storage order, then C = T x_b Ub
+    Ten t = a;
+    t.n[ia] = ua.n[0];
+    {
+        int ord[MAXP];
+        for (int r = 0; r < a.p; ++r) ord[r] = r;
+        std::stable_sort(ord, ord + a.p, [&](int x, int y) { return a.w[x] < a.w[y]; });
+        int64_t acc = 1;
+        for (int k = 0; k < a.p; ++k) {
+            t.w[ord[k]] = acc;
+            acc *= t.n[ord[k]];
+        }
+    }
+    const size_t tb = size_t(t.numel()) * size_t(esize(a.dtype));
+    plan_note("ttm2 chain dtype=%s a=%d b=%d intermediate=%zu bytes", dname(a.dtype), ma, mb, tb);
+    if (g_plan_only) return TLIB_OK;
+    t.data = workspace2(s, tb);
+    if (!t.data) return fail(TLIB_ENOMEM, "ttm2: intermediate of %zu bytes", tb);
+    if ((rc = ttm_dispatch(a, ua, ia, t, TTM_PICK_HEUR, stream))) return rc;
+    return ttm_dispatch(t, ub, ib, c, TTM_PICK_HEUR, stream);
 }
 
 int tlib_ttt(const tlib_tensor* A, const tlib_tensor* B, int32_t q, const int32_t* phi,

@@ -139,6 +139,22 @@ struct TvParams {
     double* part = nullptr;   // partial sums
 };
 
+// Two mode products in one pass: C = (A x_f Uf) x_g Ug, f the contracted
+// mode with the smaller stride in A.  Columns are the index tuples of the
+// other modes (gc: s0 = A stride, s1 = C stride).
+struct Ttm2Params {
+    const void* A = nullptr;
+    const void* Uf = nullptr;
+    const void* Ug = nullptr;
+    void* C = nullptr;
+    int32_t n_f = 1, n_g = 1, m_f = 1, m_g = 1;  // contracted extents, factor rows (<= 32)
+    int64_t s_f = 0, s_g = 0;                    // A strides of the contracted modes
+    int64_t sUf0 = 0, sUf1 = 0, sUg0 = 0, sUg1 = 0;
+    int64_t sC_f = 0, sC_g = 0;                  // C strides of j_f, j_g
+    int64_t ncol = 1;
+    Grp gc;
+};
+
 // Streaming TTM with a short contraction: X = B (M x K, strides sXm, sXk),
 // Y = A (columns nu over gn, stride sYk along k), C(j, nu) at j*sCm + gn.s1.
 struct TtmParams {
@@ -214,6 +230,9 @@ int launch_ttv_generic(int dtype, const TtvParams& p, const GDims& out, hipStrea
 int launch_gemm(int dtype, int tile, const GemmParams& p, hipStream_t s);
 // prep + main + finish kernels of the one-pass multi-mode TTV; vec: 16-byte loads
 int launch_tv(int dtype, const TvParams& P, void* c, int64_t cs, bool vec, hipStream_t s);
+int launch_ttm2(int dtype, const Ttm2Params& P, bool vec, hipStream_t s);
+int ttm2_lds_bytes(int dtype, int m_f, int n_f, int n_g, bool vec);
+int ttm2_vec_rows(int dtype);  // largest n_f of the slab-copy path
 // fm: row blocks (1, 4 or 16); ks: k-steps from ttm_stream_ks (0 = unsupported)
 int launch_ttm_stream(int dtype, const TtmParams& p, int fm, int ks, bool trans, int grid, hipStream_t s);
 int ttm_stream_ks(int dtype, int k);
@@ -240,5 +259,7 @@ int launch_axpby(int in_dtype, int out_dtype, double alpha, const void* A, doubl
 // ------------------------------------------------------------------ workspace (abi.cpp)
 // Per-(device, stream) scratch for reduction partials; grows on demand.
 void* workspace(hipStream_t s, size_t bytes);
+// A second per-stream buffer (for intermediates that must not share the first)
+void* workspace2(hipStream_t s, size_t bytes);
 
 }  // namespace tlib

@@ -24,15 +24,26 @@ def hopm(A, us: Sequence, iters: int) -> Tuple[List[float], list]:
 
 
 def tucker(A, Us: Sequence, stage_dtype=None):
-    """A x_1 U_1 x_2 U_2 ... (Sec. 5.2 tensor_times_matrices): successive mode-k
-    TTMs with factor matrices U_k of shape (r_k, n_k).  With `stage_dtype`
-    (e.g. torch.bfloat16) every intermediate is rounded to that dtype before it
+    """A x_1 U_1 x_2 U_2 ... (Sec. 5.2 tensor_times_matrices): mode products
+    with factor matrices U_k of shape (r_k, n_k), FP32/FP64 data two modes per
+    pass (ttm2), 16-bit data one TTM per mode.  With `stage_dtype` (e.g.
+    torch.bfloat16) every intermediate is rounded to that dtype before it
     enters the next TTM; results accumulate in FP32 (FP64 for FP64 data)."""
-    from . import scale, ttm
+    import torch
+
+    from . import scale, ttm, ttm2
 
     X = A
-    for k, U in enumerate(Us, start=1):
+    p = len(Us)
+    k = 1
+    while k <= p:
         if stage_dtype is not None and X.dtype != stage_dtype:
             X = scale(1.0, X, dtype=stage_dtype)
-        X = ttm(X, U, k)
+        if k < p and X.dtype in (torch.float32, torch.float64):
+            # modes k and k+1 in one pass (the intermediate is not written)
+            X = ttm2(X, Us[k - 1], k, Us[k], k + 1)
+            k += 2
+        else:
+            X = ttm(X, Us[k - 1], k)
+            k += 1
     return X

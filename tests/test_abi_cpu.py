@@ -19,7 +19,7 @@ FAKE = 1 << 40  # never dereferenced: plan-only mode
 def _declared():
     src = open(os.path.join(ROOT, "include", "tlib.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(tlib_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(tlib_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -239,3 +239,31 @@ def test_times_vectors_plans_and_errors():
         Ab = _d((n,) * 4, _lib.BF16)
         ub = [_d((n,), _lib.BF16, ptr=FAKE * (2 + k)) for k in range(4)]
         assert _tv(Ab, ub, 3, c) == 0
+
+
+def test_ttm2_plans_and_errors():
+    with Plan():
+        n = 160
+        L = _lib.lib()
+        A = _d((n,) * 4, _lib.F32, layout=(4, 3, 2, 1))
+        U = _d((32, n), _lib.F32, ptr=FAKE * 2)
+        V = _d((32, n), _lib.F32, ptr=FAKE * 3)
+        C = _d((32, 32, n, n), _lib.F32, layout=(4, 3, 2, 1), ptr=FAKE * 9)
+
+        def call(A_, U_, a, V_, b, C_):
+            return L.tlib_ttm2(ctypes.byref(A_), ctypes.byref(U_), a, ctypes.byref(V_), b, ctypes.byref(C_), None)
+
+        assert call(A, U, 1, V, 2, C) == 0 and _plan().startswith("ttm2 fused") and "f=2 g=1" in _plan()
+        # 40 factor rows: two TTMs through an intermediate
+        U40 = _d((40, n), _lib.F32, ptr=FAKE * 2)
+        C40 = _d((40, 32, n, n), _lib.F32, layout=(4, 3, 2, 1), ptr=FAKE * 9)
+        assert call(A, U40, 1, V, 2, C40) == 0 and _plan().startswith("ttm2 chain")
+        assert call(A, U, 1, V, 1, C) == _lib.EMODE
+        assert call(A, U, 0, V, 2, C) == _lib.EMODE
+        assert call(A, U, 1, V, 2, _d((32, 31, n, n), _lib.F32, ptr=FAKE * 9)) == _lib.ESHAPE
+        assert call(A, _d((32, n + 1), _lib.F32, ptr=FAKE * 2), 1, V, 2, C) == _lib.ESHAPE
+        Ab = _d((n,) * 4, _lib.BF16)
+        Ub = _d((32, n), _lib.BF16, ptr=FAKE * 2)
+        Vb = _d((32, n), _lib.BF16, ptr=FAKE * 3)
+        assert call(Ab, Ub, 1, Vb, 2, C) == _lib.EDTYPE
+        assert call(A, U, 1, V, 2, _d((32, 32, n, n), _lib.F32, ptr=FAKE + 64)) == _lib.EALIAS
