@@ -312,14 +312,36 @@ static int run_ttv(const Ten& a, const Ten& b, int mi, const Ten& c, hipStream_t
     const int64_t outs = P.n_lo * P.n_hi;
     const bool fast = nlo <= 1 && nhi <= 1 && outs < (int64_t(1) << 31) && P.n_k < (int64_t(1) << 31);
     const int es = esize(a.dtype);
+    int64_t nout = 1;
+    for (int i = 0; i < nd; ++i) nout *= d[i].n;
+    P.gh = Grp{};
+    if (fast) {
+        if (P.n_hi > 1) {
+            Dim h = {P.n_hi, {P.sA_hi, P.sC_hi, 0}};
+            fill_grp(P.gh, &h, 1, 0, 1);
+        }
+    }
+    // views whose dims do not merge: lo = the dim of smallest A stride when it
+    // is below k's and holds >= 32 outputs, hi = every other output dim
+    bool colview = false;
+    if (!fast && nd >= 1 && d[0].s[0] < P.sA_k && d[0].n >= 32 && nd - 1 <= GMAXD && nout < (int64_t(1) << 31) &&
+        P.n_k < (int64_t(1) << 31)) {
+        P.n_lo = d[0].n;
+        P.sA_lo = d[0].s[0];
+        P.sC_lo = d[0].s[1];
+        colview = fill_grp(P.gh, d + 1, nd - 1, 0, 1);
+        P.n_hi = P.gh.total;
+        P.sA_hi = P.sC_hi = 0;
+    }
 
-    if (fast && P.n_lo >= 32) {
+    if ((fast && P.n_lo >= 32) || colview) {
         const int maxvec = 16 / es;
         auto vec_ok = [&](int v) {
             if (v == 1) return true;
             if (P.sA_lo != 1 || P.n_lo % v) return false;
             if (P.n_k > 1 && P.sA_k % v) return false;
-            if (P.n_hi > 1 && P.sA_hi % v) return false;
+            for (int j = 0; j < P.gh.nd; ++j)
+                if (P.gh.n[j] > 1 && P.gh.s0[j] % v) return false;
             return (uintptr_t(P.A) % (uintptr_t)(v * es)) == 0;
         };
         auto blocks = [&](int v) { return ((P.n_lo + 64 * v - 1) / (64 * v)) * P.n_hi; };
@@ -336,10 +358,10 @@ static int run_ttv(const Ten& a, const Ten& b, int mi, const Ten& c, hipStream_t
         void* ws = nullptr;
         size_t wsb = ks > 1 ? size_t(ks) * size_t(outs) * size_t(esize(acc_dtype(a.dtype))) : 0;
         plan_note("ttv col dtype=%s n_lo=%lld n_k=%lld n_hi=%lld sA=(%lld,%lld,%lld) sC=(%lld,%lld) "
-                  "vec=%d ksplit=%d blocks=%lld",
+                  "hidims=%d vec=%d ksplit=%d blocks=%lld",
                   dname(a.dtype), (long long)P.n_lo, (long long)P.n_k, (long long)P.n_hi,
                   (long long)P.sA_lo, (long long)P.sA_k, (long long)P.sA_hi, (long long)P.sC_lo,
-                  (long long)P.sC_hi, vec, ks, (long long)(nb * ks));
+                  (long long)P.sC_hi, P.gh.nd, vec, ks, (long long)(nb * ks));
         if (g_plan_only) return TLIB_OK;
         if (ks > 1) {
             ws = workspace(s, wsb);
@@ -373,6 +395,18 @@ static int run_ttv(const Ten& a, const Ten& b, int mi, const Ten& c, hipStream_t
         if (g_plan_only) return TLIB_OK;
         int rc = launch_ttv_slab(a.dtype, P, int(S), int(kc), s);
         return rc ? fail(rc, "ttv: launch failed") : TLIB_OK;
+    }
+    // views with slabs that are not contiguous: G lanes per output fiber
+    {
+        Grp go;
+        if (nd <= GMAXD && nout < (int64_t(1) << 31) && P.n_k < (int64_t(1) << 31) && fill_grp(go, d, nd, 0, 1)) {
+            const int G = P.n_k >= 256 ? 64 : P.n_k >= 64 ? 32 : P.n_k >= 16 ? 16 : 8;
+            plan_note("ttv fiber dtype=%s dims=%d outputs=%lld n_k=%lld sA_k=%lld G=%d", dname(a.dtype), nd,
+                      (long long)nout, (long long)P.n_k, (long long)P.sA_k, G);
+            if (g_plan_only) return TLIB_OK;
+            int rc = launch_ttv_fiber(a.dtype, P, go, G, s);
+            return rc ? fail(rc, "ttv: launch failed") : TLIB_OK;
+        }
     }
     GDims g;
     fill_gdims(g, d, nd, 2);

@@ -78,6 +78,9 @@ struct TtvParams {
     void* C;
     int64_t n_lo, n_k, n_hi;
     int64_t sA_lo, sA_k, sA_hi, sb, sC_lo, sC_hi;
+    // col kernel: the hi index decoded over up to GMAXD dims (s0 = A stride,
+    // s1 = C stride), so views whose outer dims do not merge keep the kernel
+    Grp gh;
 };
 
 struct GemmParams {
@@ -226,6 +229,8 @@ TileShape tile_shape(int t);
 int launch_ttv_col(int dtype, const TtvParams& p, int vec, int ksplit, void* ws, hipStream_t s);
 int launch_ttv_slab(int dtype, const TtvParams& p, int slabs, int kc, hipStream_t s);
 int launch_ttv_generic(int dtype, const TtvParams& p, const GDims& out, hipStream_t s);
+// G lanes per output stream its k-fiber; outputs decoded over go (s0 = A, s1 = C)
+int launch_ttv_fiber(int dtype, const TtvParams& p, const Grp& go, int G, hipStream_t s);
 
 int launch_gemm(int dtype, int tile, const GemmParams& p, hipStream_t s);
 // prep + main + finish kernels of the one-pass multi-mode TTV; vec: 16-byte loads

@@ -3,9 +3,10 @@
 // also serves relayout and transposition (a permuted stride tuple for A).
 //
 // inner/norm: two passes with a fixed partition (a block per contiguous range
-// of the collapsed iteration space, a fixed shuffle/LDS tree inside the block,
-// then one block summing the partials in index order), so the FP64 result only
-// depends on the shapes and strides, never on scheduling.
+// of the collapsed iteration space, or per range of rows of the innermost dim
+// when the dims of a view do not merge, a fixed shuffle/LDS tree inside the
+// block, then one block summing the partials in index order), so the FP64
+// result only depends on the shapes and strides, never on scheduling.
 #include <algorithm>
 
 #include "device.hpp"
@@ -27,18 +28,20 @@ __global__ __launch_bounds__(DOT_BLOCK) void dot_pass1(const TI* A, const TI* B,
     const int tid = threadIdx.x;
     const int64_t beg = int64_t(blockIdx.x) * chunk;
     const int64_t end = min(g.total, beg + chunk);
-    const bool flat = g.nd <= 1 && g.s[0][0] == 1 && g.s[1][0] == 1;
+    // one dim (any strides): a strided flat walk
+    const bool flat = g.nd <= 1;
+    const int64_t sa = g.nd == 1 ? g.s[0][0] : 0, sb = g.nd == 1 ? g.s[1][0] : 0;
     double acc = 0.0;
     if (flat) {
         int64_t i = beg + tid;
         for (; i + 3 * DOT_BLOCK < end; i += 4 * DOT_BLOCK) {
-            const double a0 = to_f64(A[i]), a1 = to_f64(A[i + DOT_BLOCK]);
-            const double a2 = to_f64(A[i + 2 * DOT_BLOCK]), a3 = to_f64(A[i + 3 * DOT_BLOCK]);
+            const double a0 = to_f64(A[i * sa]), a1 = to_f64(A[(i + DOT_BLOCK) * sa]);
+            const double a2 = to_f64(A[(i + 2 * DOT_BLOCK) * sa]), a3 = to_f64(A[(i + 3 * DOT_BLOCK) * sa]);
             if (B) {
-                acc += a0 * to_f64(B[i]);
-                acc += a1 * to_f64(B[i + DOT_BLOCK]);
-                acc += a2 * to_f64(B[i + 2 * DOT_BLOCK]);
-                acc += a3 * to_f64(B[i + 3 * DOT_BLOCK]);
+                acc += a0 * to_f64(B[i * sb]);
+                acc += a1 * to_f64(B[(i + DOT_BLOCK) * sb]);
+                acc += a2 * to_f64(B[(i + 2 * DOT_BLOCK) * sb]);
+                acc += a3 * to_f64(B[(i + 3 * DOT_BLOCK) * sb]);
             } else {
                 acc += a0 * a0;
                 acc += a1 * a1;
@@ -47,8 +50,8 @@ __global__ __launch_bounds__(DOT_BLOCK) void dot_pass1(const TI* A, const TI* B,
             }
         }
         for (; i < end; i += DOT_BLOCK) {
-            const double a = to_f64(A[i]);
-            acc += a * (B ? to_f64(B[i]) : a);
+            const double a = to_f64(A[i * sa]);
+            acc += a * (B ? to_f64(B[i * sb]) : a);
         }
     } else {
         for (int64_t i = beg + tid; i < end; i += DOT_BLOCK) {
@@ -56,6 +59,57 @@ __global__ __launch_bounds__(DOT_BLOCK) void dot_pass1(const TI* A, const TI* B,
             gd_decode(i, g, 2, off);
             const double a = to_f64(A[off[0]]);
             acc += a * (B ? to_f64(B[off[1]]) : a);
+        }
+    }
+    acc = warp_sum(acc, 64);
+    __shared__ double red[DOT_BLOCK / 64];
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// Views whose dims do not merge: rows along the innermost dim (g.n[0]
+// elements), each row's offsets decoded once over the other dims, G lanes per
+// row streaming it; workgroup b owns rows [b rpb, (b+1) rpb).  The partition
+// and every summation order are fixed.
+template <typename TI>
+__global__ __launch_bounds__(DOT_BLOCK) void dot_rows(const TI* A, const TI* B, GDims g, int64_t rows, int64_t rpb,
+                                                      int G, double* part) {
+    const int tid = threadIdx.x;
+    const int gi = tid / G, l = tid % G, per = DOT_BLOCK / G;
+    const int64_t r0 = int64_t(blockIdx.x) * rpb, r1 = min(rows, r0 + rpb);
+    const int64_t n0 = g.n[0], sa = g.s[0][0], sb = g.s[1][0];
+    double acc = 0.0;
+    for (int64_t r = r0 + gi; r < r1; r += per) {
+        int64_t lin = r, oa = 0, ob = 0;
+        for (int d = 1; d < g.nd; ++d) {
+            const int64_t q = d == g.nd - 1 ? 0 : lin / g.n[d];
+            const int64_t rr = lin - q * g.n[d];
+            oa += rr * g.s[0][d];
+            ob += rr * g.s[1][d];
+            lin = q;
+        }
+        const TI* a = A + oa;
+        const TI* b = B ? B + ob : nullptr;
+        int64_t c = l;
+        for (; c + 3 * G < n0; c += 4 * G) {
+            const double a0 = to_f64(a[c * sa]), a1 = to_f64(a[(c + G) * sa]);
+            const double a2 = to_f64(a[(c + 2 * G) * sa]), a3 = to_f64(a[(c + 3 * G) * sa]);
+            if (b) {
+                acc += a0 * to_f64(b[c * sb]);
+                acc += a1 * to_f64(b[(c + G) * sb]);
+                acc += a2 * to_f64(b[(c + 2 * G) * sb]);
+                acc += a3 * to_f64(b[(c + 3 * G) * sb]);
+            } else {
+                acc += a0 * a0;
+                acc += a1 * a1;
+                acc += a2 * a2;
+                acc += a3 * a3;
+            }
+        }
+        for (; c < n0; c += G) {
+            const double x = to_f64(a[c * sa]);
+            acc += x * (b ? to_f64(b[c * sb]) : x);
         }
     }
     acc = warp_sum(acc, 64);
@@ -82,10 +136,19 @@ __global__ __launch_bounds__(DOT_BLOCK) void dot_pass2(const double* part, int n
 template <typename TI>
 static int dot_launch(const void* A, const void* B, const GDims& g, double* out, bool sq, void* ws,
                       hipStream_t s) {
-    const int np = dot_partials(g.total);
-    const int64_t chunk = (g.total + np - 1) / np;
-    hipLaunchKernelGGL((dot_pass1<TI>), dim3(np), dim3(DOT_BLOCK), 0, s, (const TI*)A, (const TI*)B, g, chunk,
-                       (double*)ws);
+    int np = dot_partials(g.total);
+    if (g.nd >= 2) {
+        const int64_t rows = g.total / g.n[0];
+        const int G = g.n[0] >= 256 ? 64 : g.n[0] >= 64 ? 32 : g.n[0] >= 16 ? 16 : 8;
+        const int64_t rpb = (rows + np - 1) / np;
+        np = int((rows + rpb - 1) / rpb);
+        hipLaunchKernelGGL((dot_rows<TI>), dim3(np), dim3(DOT_BLOCK), 0, s, (const TI*)A, (const TI*)B, g, rows, rpb,
+                           G, (double*)ws);
+    } else {
+        const int64_t chunk = (g.total + np - 1) / np;
+        hipLaunchKernelGGL((dot_pass1<TI>), dim3(np), dim3(DOT_BLOCK), 0, s, (const TI*)A, (const TI*)B, g, chunk,
+                           (double*)ws);
+    }
     if (hipGetLastError() != hipSuccess) return TLIB_EHIP;
     hipLaunchKernelGGL(dot_pass2, dim3(1), dim3(DOT_BLOCK), 0, s, (const double*)ws, np, out, sq ? 1 : 0);
     return hipGetLastError() == hipSuccess ? TLIB_OK : TLIB_EHIP;

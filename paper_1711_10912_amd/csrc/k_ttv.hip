@@ -5,10 +5,15 @@
 // kernels are organised around coalesced reads of A:
 //   col   (n_lo >= 32): lanes run along lo (unit stride), the four waves of a
 //         workgroup take interleaved k and are summed through LDS in a fixed
-//         order; optional grid split over k with a second summing pass.
+//         order; optional grid split over k with a second summing pass.  The
+//         hi index is decoded over up to four dims, so views whose outer dims
+//         do not merge (ranges, steps) stay on this kernel.
 //   slab  (n_lo < 32 and the (lo,k) slabs contiguous): a workgroup copies whole
 //         contiguous slabs into LDS with coalesced loads, then groups of G lanes
 //         reduce each output's k-fiber out of LDS with a shuffle tree.
+//   fiber (n_lo < 32, slabs not contiguous: views): G lanes per output stream
+//         its k-fiber (coalesced when k has unit stride) and reduce with a
+//         fixed shuffle tree; outputs decoded over up to four dims.
 //   generic: one thread per output, any strides.
 // Accumulation is in FP64 for FP64 inputs and in FP32 otherwise.
 #include <algorithm>
@@ -45,12 +50,14 @@ __global__ __launch_bounds__(256) void ttv_col_kernel(TtvParams P, int64_t lo_ti
     const int64_t kb = ks * kchunk;
     const int64_t ke = min(P.n_k, kb + kchunk);
     const bool active = lo0 < P.n_lo;
+    int64_t hA, hC;
+    grp_decode(uint32_t(hi), P.gh, hA, hC);
 
     TA acc[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) acc[v] = TA(0);
     if (active) {
-        const TI* Ap = (const TI*)P.A + hi * P.sA_hi + lo0 * P.sA_lo;
+        const TI* Ap = (const TI*)P.A + hA + lo0 * P.sA_lo;
         const TI* b = (const TI*)P.b;
         int64_t k = kb + wave;
         // four rows in flight per wave
@@ -98,7 +105,7 @@ __global__ __launch_bounds__(256) void ttv_col_kernel(TtvParams P, int64_t lo_ti
             const TA s = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
             const int64_t lo = lo0 + v;
             if (part) part[ks * (P.n_lo * P.n_hi) + hi * P.n_lo + lo] = s;
-            else C[lo * P.sC_lo + hi * P.sC_hi] = s;
+            else C[lo * P.sC_lo + hC] = s;
         }
     }
 }
@@ -110,7 +117,7 @@ __global__ __launch_bounds__(256) void ttv_ksum_kernel(TtvParams P, int ksplit, 
         TA s = part[o];
         for (int k = 1; k < ksplit; ++k) s += part[int64_t(k) * outs + o];
         const int64_t lo = o % P.n_lo, hi = o / P.n_lo;
-        ((TA*)P.C)[lo * P.sC_lo + hi * P.sC_hi] = s;
+        ((TA*)P.C)[lo * P.sC_lo + grp_off1(uint32_t(hi), P.gh)] = s;
     }
 }
 
@@ -201,6 +208,40 @@ __global__ __launch_bounds__(256) void ttv_slab_kernel(TtvParams P, int slabs, i
 }
 
 template <typename TI>
+__global__ __launch_bounds__(256) void ttv_fiber_kernel(TtvParams P, Grp go, int G, int64_t outs) {
+    using TA = typename AccOf<TI>::type;
+    const TI* A = (const TI*)P.A;
+    const TI* b = (const TI*)P.b;
+    TA* C = (TA*)P.C;
+    const int g = threadIdx.x % G;
+    const int64_t per = 256 / G;
+    // the outer loop runs the same rounds for every thread of the block
+    // (outputs past the end take a zero-length fiber), so every shuffle sees
+    // all lanes of its group
+    for (int64_t o0 = int64_t(blockIdx.x) * per; o0 < outs; o0 += int64_t(gridDim.x) * per) {
+        const int64_t o = o0 + threadIdx.x / G;
+        const bool ok = o < outs;
+        int64_t oa, oc;
+        grp_decode(uint32_t(ok ? o : 0), go, oa, oc);
+        const TI* a = A + oa;
+        const int64_t nk = ok ? P.n_k : 0;
+        TA acc = TA(0);
+        int64_t k = g;
+        for (; k + 3 * G < nk; k += 4 * G) {
+            const TA x0 = to_acc(a[k * P.sA_k]), x1 = to_acc(a[(k + G) * P.sA_k]);
+            const TA x2 = to_acc(a[(k + 2 * G) * P.sA_k]), x3 = to_acc(a[(k + 3 * G) * P.sA_k]);
+            acc += x0 * to_acc(b[k * P.sb]);
+            acc += x1 * to_acc(b[(k + G) * P.sb]);
+            acc += x2 * to_acc(b[(k + 2 * G) * P.sb]);
+            acc += x3 * to_acc(b[(k + 3 * G) * P.sb]);
+        }
+        for (; k < nk; k += G) acc += to_acc(a[k * P.sA_k]) * to_acc(b[k * P.sb]);
+        acc = warp_sum(acc, G);
+        if (ok && g == 0) C[oc] = acc;
+    }
+}
+
+template <typename TI>
 __global__ __launch_bounds__(256) void ttv_generic_kernel(TtvParams P, GDims g) {
     using TA = typename AccOf<TI>::type;
     const TI* A = (const TI*)P.A;
@@ -270,6 +311,25 @@ int launch_ttv_slab(int dtype, const TtvParams& p, int slabs, int kc, hipStream_
         case TLIB_F32: return slab_launch<float>(p, slabs, kc, s);
         case TLIB_BF16: return slab_launch<bf16_t>(p, slabs, kc, s);
         case TLIB_F16: return slab_launch<f16_t>(p, slabs, kc, s);
+    }
+    return TLIB_EDTYPE;
+}
+
+template <typename TI>
+static int fiber_launch(const TtvParams& p, const Grp& go, int G, hipStream_t s) {
+    const int64_t outs = go.total;
+    const int64_t per = 256 / G;
+    const unsigned blocks = unsigned(std::max<int64_t>(1, std::min<int64_t>((outs + per - 1) / per, 8192)));
+    hipLaunchKernelGGL((ttv_fiber_kernel<TI>), dim3(blocks), dim3(256), 0, s, p, go, G, outs);
+    return hipGetLastError() == hipSuccess ? TLIB_OK : TLIB_EHIP;
+}
+
+int launch_ttv_fiber(int dtype, const TtvParams& p, const Grp& go, int G, hipStream_t s) {
+    switch (dtype) {
+        case TLIB_F64: return fiber_launch<double>(p, go, G, s);
+        case TLIB_F32: return fiber_launch<float>(p, go, G, s);
+        case TLIB_BF16: return fiber_launch<bf16_t>(p, go, G, s);
+        case TLIB_F16: return fiber_launch<f16_t>(p, go, G, s);
     }
     return TLIB_EDTYPE;
 }

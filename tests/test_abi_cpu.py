@@ -79,11 +79,23 @@ def test_ttv_regimes():
         A = _d((n, n, n), layout=(3, 2, 1))
         Cl = _d((n, n), layout=(2, 1), ptr=FAKE * 3)
         assert _ttv(A, b, 3, Cl) == 0 and _plan().startswith("ttv slab")
-        # a C layout that does not follow A's: generic kernel
+        # a C layout that does not follow A's: the dims do not merge, short lo
+        # (13 < 32): one fiber per output
         A = _d((13,) * 4)
         b = _d((13,), ptr=FAKE * 2)
         C = _d((13,) * 3, layout=(3, 1, 2), ptr=FAKE * 3)
-        assert _ttv(A, b, 2, C) == 0 and _plan().startswith("ttv generic")
+        assert _ttv(A, b, 2, C) == 0 and _plan().startswith("ttv fiber")
+        # a view with gaps (every other index of mode 1, trimmed mode 2): col
+        # kernel with the hi index over two dims
+        Av = _d((64, 30, 20), strides=(2, 200, 10000))
+        bv = _d((20,), ptr=FAKE * 2)
+        Cv = _d((64, 30), ptr=FAKE * 3)
+        assert _ttv(Av, bv, 3, Cv) == 0 and _plan().startswith("ttv col") and "hidims=1" in _plan()
+        # five output dims that merge with nothing: generic kernel
+        A6 = _d((3, 4, 5, 6, 7, 2))
+        b6 = _d((3,), ptr=FAKE * 2)
+        C6 = _d((4, 5, 6, 7, 2), layout=(5, 4, 3, 2, 1), ptr=FAKE * 3)
+        assert _ttv(A6, b6, 1, C6) == 0 and _plan().startswith("ttv generic")
 
 
 def test_ttm_and_ttt_plans():
