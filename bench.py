@@ -447,6 +447,92 @@ def drivers_bench(args):
     }
 
 
+def views_bench(args):
+    """Operations on strided views (ranges with steps) of order-4 90^4 tensors
+    against the same operations on dense tensors of the same logical shape:
+    TTV in every mode, TTM (m = 64) in modes 1 and 4, norm, inner and add.
+    Bytes are the useful ones (the view's elements, outputs, operands)."""
+    import torch
+
+    import paper_1711_10912_amd as T
+
+    dev = torch.device("cuda:0")
+    n, m = 90, 64
+    reps = max(1, args.steps)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    out = {}
+    totals = {}
+    for dname_, dt in (("f32", torch.float32), ("f64", torch.float64)):
+        s = 4 if dt == torch.float32 else 8
+        g = torch.Generator(device=dev)
+        g.manual_seed(171110912 + 5)
+        views = {
+            "dense": T.empty((n, n, n, n), None, dt, dev),
+            "sliced": T.empty((2 * n, n + 3, n, n), None, dt, dev)[:n, :n],
+            "step2_mode1": T.empty((2 * n, n, n, n), None, dt, dev)[::2],
+            "trim": T.empty((n + 2, n + 2, n + 2, n + 2), None, dt, dev)[1:n + 1, 1:n + 1, 1:n + 1, 1:n + 1],
+            "step3_mode2_last": T.empty((n, 3 * n, n, n), [4, 3, 2, 1], dt, dev)[:, ::3],
+            "step2_mode4_perm": T.empty((n, n, n, 2 * n), [2, 4, 1, 3], dt, dev)[:, :, :, ::2],
+        }
+        for name, A in views.items():
+            A.copy_(torch.rand(A.shape, generator=g, device=dev, dtype=dt))
+            N = A.numel()
+            ops = []
+            for q in range(1, 5):
+                b = torch.rand(n, generator=g, device=dev, dtype=dt)
+                C = T.ttv(A, b, q)
+                ops.append(("ttv q=%d" % q, s * (N + N // n + n), (lambda A=A, b=b, q=q, C=C: T.ttv(A, b, q, out=C)),
+                            T.plan(T.ttv, A, b, q, out=C).split(" ")[1]))
+            for q in (1, 4):
+                B = torch.rand(m, n, generator=g, device=dev, dtype=dt)
+                C = T.ttm(A, B, q)
+                ops.append(("ttm q=%d m=%d" % (q, m), s * (N + N // n * m + m * n),
+                            (lambda A=A, B=B, q=q, C=C: T.ttm(A, B, q, out=C)),
+                            T.plan(T.ttm, A, B, q, out=C).split(" ")[1]))
+            r = torch.empty((), dtype=torch.float64, device=dev)
+            ops.append(("norm", s * N, (lambda A=A, r=r: T.norm(A, out=r)), "dot"))
+            ops.append(("inner", 2 * s * N, (lambda A=A, r=r: T.inner(A, A, out=r)), "dot"))
+            Cd = T.empty(A.shape, None, dt, dev)
+            ops.append(("add", 3 * s * N, (lambda A=A, Cd=Cd: T.add(1.0, A, 1.0, A, out=Cd)), "ewise"))
+            rec = {}
+            tb = tt = 0.0
+            for label, nbytes, fn, kern in ops:
+                t = timed(fn)
+                rec[label] = {"us": round(t * 1e6, 1), "GB/s": round(nbytes / t / 1e9, 1), "kernel": kern}
+                tb += nbytes
+                tt += t
+            out["%s %s" % (dname_, name)] = rec
+            totals["%s %s" % (dname_, name)] = tb / tt / 1e9
+        del views
+        torch.cuda.empty_cache()
+    view_keys = [k for k in totals if not k.endswith("dense")]
+    value = sum(totals[k] for k in view_keys) / len(view_keys)
+    return {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "GB/s (mean over views and dtypes of useful bytes / time for TTV, TTM, norm, inner, add)",
+        "n_gpus": 1, "steps": reps, "warmup": 1,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32, f64", "data": "synthetic: U[0,1) views of 90^4 tensors (seeded)",
+        "config": {"workload": "strided views (ranges with steps) of order-4 90^4 tensors"},
+        "dense_reference_GB/s": {k: round(v, 1) for k, v in totals.items() if k.endswith("dense")},
+        "views_GB/s": {k: round(v, 1) for k, v in totals.items() if not k.endswith("dense")},
+        "ops": out,
+    }
+
+
 def run_step(cases, torch, ev):
     for i, c in enumerate(cases):
         if ev is not None:
@@ -519,9 +605,10 @@ def main():
     ap.add_argument("--autotune-save", default="", help="write the table after the first warmup step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cases-out", default="", help="write per-case timings (JSON lines) here")
-    ap.add_argument("--workload", default="sweep", choices=("sweep", "serve", "drivers"),
+    ap.add_argument("--workload", default="sweep", choices=("sweep", "serve", "drivers", "views"),
                     help="sweep: the order-p TTV/TTM sweep + TTT (default); serve: the served "
-                         "mixed request stream (latency / req/s)")
+                         "mixed request stream (latency / req/s); drivers: Tucker, multi-mode TTV, HOPM; "
+                         "views: operations on strided views against dense tensors")
     ap.add_argument("--requests", type=int, default=10000, help="serve: stream length")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (3 times), the reference for the "
@@ -551,6 +638,9 @@ def main():
         return
     if args.workload == "drivers":
         print(json.dumps(drivers_bench(args)))
+        return
+    if args.workload == "views":
+        print(json.dumps(views_bench(args)))
         return
 
     dev = torch.device("cuda:0")
