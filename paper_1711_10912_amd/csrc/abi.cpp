@@ -1175,6 +1175,46 @@ static int run_axpby(double alpha, const Ten& a, double beta, const Ten* b, cons
     // slot 1 holds B's strides; without B it repeats C's so that it never blocks a merge
     for (int r = 0; r < c.p; ++r) d[r] = {c.n[r], {wA_by_c[r], b ? b->w[r] : c.w[r], c.w[r]}};
     int nd = coalesce(d, c.p, 3, 2);
+    // C's fastest dim is d[0]; when A's fastest is another dim y, go through
+    // LDS tiles so that A is read along y and C written along x.
+    int y = -1;
+    for (int i = 1; i < nd; ++i)
+        if (y < 0 || d[i].s[0] < d[y].s[0]) y = i;
+    if (y > 0 && d[0].s[2] == 1 && d[y].s[0] >= 1 && d[y].s[0] <= 2 && d[0].s[0] > 8 * d[y].s[0] &&
+        d[0].n >= 16 && d[y].n >= 16) {
+        EwTile t;
+        t.nx = d[0].n;
+        t.ny = d[y].n;
+        for (int o = 0; o < 3; ++o) {
+            t.sx[o] = d[0].s[o];
+            t.sy[o] = d[y].s[o];
+        }
+        int64_t nrest = 1;
+        for (int i = 1; i < nd; ++i) {
+            if (i == y) continue;
+            t.rn[t.nr] = uint32_t(d[i].n);
+            t.rfd[t.nr] = make_fastdiv(uint32_t(d[i].n));
+            for (int o = 0; o < 3; ++o) t.rs[o][t.nr] = d[i].s[o];
+            ++t.nr;
+            nrest *= d[i].n;
+        }
+        const int64_t tx = (t.nx + EW_T - 1) / EW_T, ty = (t.ny + EW_T - 1) / EW_T;
+        const int64_t ntiles = tx * ty * ((nrest + EW_RZ - 1) / EW_RZ);
+        if (ntiles < (int64_t(1) << 31) && nrest < (int64_t(1) << 31)) {
+            t.tx = uint32_t(tx);
+            t.ty = uint32_t(ty);
+            t.ftx = make_fastdiv(t.tx);
+            t.fty = make_fastdiv(t.ty);
+            t.nrest = uint32_t(nrest);
+            t.ntiles = uint32_t(ntiles);
+            const int bm = !b ? 0 : (d[y].s[1] < d[0].s[1] ? 2 : 1);
+            plan_note("%s ewise tile dtype=%s->%s x=%lld y=%lld rest=%lld b=%d tiles=%lld", op, dname(a.dtype),
+                      dname(c.dtype), (long long)t.nx, (long long)t.ny, (long long)nrest, bm, (long long)ntiles);
+            if (g_plan_only) return TLIB_OK;
+            int rc = launch_axpby_tile(a.dtype, c.dtype, alpha, a.data, beta, b ? b->data : nullptr, c.data, t, bm, s);
+            return rc ? fail(rc, "%s: launch failed", op) : TLIB_OK;
+        }
+    }
     GDims g;
     fill_gdims(g, d, nd, 3);
     plan_note("%s ewise dtype=%s->%s dims=%d total=%lld%s", op, dname(a.dtype), dname(c.dtype), nd, (long long)g.total,

@@ -69,6 +69,22 @@ struct GDims {
     int64_t s[3][MAXP] = {};
 };
 
+// Entrywise op whose output's fastest dimension (x) is not the input's (y):
+// 32x32 tiles over (x, y) times slices of the other dims; 32-bit fast-divide
+// decode.  Strides: operand 0 = A, 1 = B, 2 = C.
+constexpr int EW_T = 32;   // tile edge
+constexpr int EW_RZ = 2;   // slices of the other dims per tile
+struct EwTile {
+    int64_t nx = 1, ny = 1;
+    int64_t sx[3] = {}, sy[3] = {};
+    uint32_t tx = 1, ty = 1, nrest = 1, ntiles = 1;
+    FastDiv ftx, fty;
+    int nr = 0;
+    uint32_t rn[MAXP] = {};
+    FastDiv rfd[MAXP];
+    int64_t rs[3][MAXP] = {};
+};
+
 // ------------------------------------------------------------------ kernel parameters
 
 // TTV on the collapsed (lo, k, hi) form: A(lo,k,hi) at lo*sA_lo + k*sA_k + hi*sA_hi.
@@ -260,6 +276,10 @@ int dot_partials(int64_t total);  // number of first-pass partials for a given s
 // A and B have in_dtype; C has out_dtype (correctly rounded from FP64).
 int launch_axpby(int in_dtype, int out_dtype, double alpha, const void* A, double beta, const void* B,
                  void* C, const GDims& d, hipStream_t s);
+// The same op through LDS tiles (EwTile); b_mode 0 = no B, 1 = B read along x
+// (laid out like C), 2 = B read along y (laid out like A).
+int launch_axpby_tile(int in_dtype, int out_dtype, double alpha, const void* A, double beta, const void* B,
+                      void* C, const EwTile& t, int b_mode, hipStream_t s);
 
 // ------------------------------------------------------------------ workspace (abi.cpp)
 // Per-(device, stream) scratch for reduction partials; grows on demand.

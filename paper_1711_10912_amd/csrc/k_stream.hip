@@ -244,4 +244,130 @@ int launch_axpby(int in_dtype, int out_dtype, double alpha, const void* A, doubl
     return TLIB_EDTYPE;
 }
 
+// ------------------------------------------------------------------ tiled relayout
+// The same entrywise op when C's fastest dimension x is not A's fastest y
+// (a transpose, or add/scale into another layout).  A block owns a 32 x 32
+// tile of (x, y) for EW_RZ slices of the remaining dims: it reads A (and B
+// when B is laid out like A) with consecutive lanes along y, parks the values
+// in LDS, and writes C (reading B there when B is laid out like C) with
+// consecutive lanes along x, so both HBM streams move whole 128-B lines.
+// Arithmetic is axpby_kernel's, element for element.
+__device__ uint64_t g_ew_zero[2];
+
+__device__ __forceinline__ void ew_rest(uint32_t r, const EwTile& P, int64_t* o) {
+    o[0] = o[1] = o[2] = 0;
+#pragma unroll
+    for (int d = 0; d < MAXP; ++d) {
+        if (d >= P.nr) break;
+        const uint32_t q = (d == P.nr - 1) ? 0u : fdiv(r, P.rfd[d]);
+        const int64_t i = int64_t(r - q * P.rn[d]);
+        o[0] += i * P.rs[0][d];
+        o[1] += i * P.rs[1][d];
+        o[2] += i * P.rs[2][d];
+        r = q;
+    }
+}
+
+template <typename TI, typename TO, int BM>
+__global__ __launch_bounds__(256) void axpby_tile_kernel(double alpha, const TI* A, double beta, const TI* B,
+                                                         TO* C, EwTile P) {
+#pragma clang fp contract(off)
+    constexpr int TS = EW_RZ * EW_T * (EW_T + 1);
+    __shared__ __align__(8) unsigned char smem[(BM == 2 ? 2 : 1) * TS * sizeof(TI)];
+    TI* ta = reinterpret_cast<TI*>(smem);
+    TI* tb = ta + TS;
+    const TI* zs = reinterpret_cast<const TI*>(g_ew_zero);
+    const int lx = threadIdx.x & (EW_T - 1), ly = threadIdx.x / EW_T;  // 32 x 8
+    for (uint32_t t = blockIdx.x; t < P.ntiles; t += gridDim.x) {
+        const uint32_t q = fdiv(t, P.ftx);
+        const int64_t x0 = int64_t(t - q * P.tx) * EW_T;
+        const uint32_t rb = fdiv(q, P.fty);
+        const int64_t y0 = int64_t(q - rb * P.ty) * EW_T;
+        int64_t ro[EW_RZ][3];
+        bool rv[EW_RZ];
+#pragma unroll
+        for (int z = 0; z < EW_RZ; ++z) {
+            const uint32_t r = rb * EW_RZ + z;
+            rv[z] = r < P.nrest;
+            ew_rest(rv[z] ? r : 0u, P, ro[z]);
+        }
+        // read phase: lanes along y
+        TI va[EW_RZ][EW_T / 8], vb[EW_RZ][EW_T / 8];
+        const int64_t yr = y0 + lx;
+#pragma unroll
+        for (int z = 0; z < EW_RZ; ++z)
+#pragma unroll
+            for (int j = 0; j < EW_T / 8; ++j) {
+                const int64_t xr = x0 + ly + 8 * j;
+                const bool ok = rv[z] && xr < P.nx && yr < P.ny;
+                va[z][j] = *(ok ? A + (ro[z][0] + xr * P.sx[0] + yr * P.sy[0]) : zs);
+                if (BM == 2) vb[z][j] = *(ok ? B + (ro[z][1] + xr * P.sx[1] + yr * P.sy[1]) : zs);
+            }
+        __syncthreads();
+#pragma unroll
+        for (int z = 0; z < EW_RZ; ++z)
+#pragma unroll
+            for (int j = 0; j < EW_T / 8; ++j) {
+                const int e = (z * EW_T + ly + 8 * j) * (EW_T + 1) + lx;
+                ta[e] = va[z][j];
+                if (BM == 2) tb[e] = vb[z][j];
+            }
+        __syncthreads();
+        // write phase: lanes along x
+        const int64_t xw = x0 + lx;
+#pragma unroll
+        for (int z = 0; z < EW_RZ; ++z)
+#pragma unroll
+            for (int j = 0; j < EW_T / 8; ++j) {
+                const int64_t yw = y0 + ly + 8 * j;
+                const bool ok = rv[z] && xw < P.nx && yw < P.ny;
+                const int e = (z * EW_T + lx) * (EW_T + 1) + ly + 8 * j;
+                double v = alpha * to_f64(ta[e]);
+                if (BM == 1) v = v + beta * to_f64(*(ok ? B + (ro[z][1] + xw * P.sx[1] + yw * P.sy[1]) : zs));
+                if (BM == 2) v = v + beta * to_f64(tb[e]);
+                if (ok) C[ro[z][2] + xw * P.sx[2] + yw * P.sy[2]] = round_out<TO>(v);
+            }
+    }
+}
+
+template <typename TI, typename TO>
+static int axpby_tile_launch(double alpha, const void* A, double beta, const void* B, void* C, const EwTile& t,
+                             int bm, hipStream_t s) {
+    const unsigned blocks = unsigned(std::max<uint32_t>(1, std::min<uint32_t>(t.ntiles, 1u << 20)));
+    if (bm == 0)
+        hipLaunchKernelGGL((axpby_tile_kernel<TI, TO, 0>), dim3(blocks), dim3(256), 0, s, alpha, (const TI*)A,
+                           beta, (const TI*)B, (TO*)C, t);
+    else if (bm == 1)
+        hipLaunchKernelGGL((axpby_tile_kernel<TI, TO, 1>), dim3(blocks), dim3(256), 0, s, alpha, (const TI*)A,
+                           beta, (const TI*)B, (TO*)C, t);
+    else
+        hipLaunchKernelGGL((axpby_tile_kernel<TI, TO, 2>), dim3(blocks), dim3(256), 0, s, alpha, (const TI*)A,
+                           beta, (const TI*)B, (TO*)C, t);
+    return hipGetLastError() == hipSuccess ? TLIB_OK : TLIB_EHIP;
+}
+
+template <typename TI>
+static int axpby_tile_out(int out_dtype, double alpha, const void* A, double beta, const void* B, void* C,
+                          const EwTile& t, int bm, hipStream_t s) {
+    switch (out_dtype) {
+        case TLIB_F64: return axpby_tile_launch<TI, double>(alpha, A, beta, B, C, t, bm, s);
+        case TLIB_F32: return axpby_tile_launch<TI, float>(alpha, A, beta, B, C, t, bm, s);
+        case TLIB_BF16: return axpby_tile_launch<TI, bf16_t>(alpha, A, beta, B, C, t, bm, s);
+        case TLIB_F16: return axpby_tile_launch<TI, f16_t>(alpha, A, beta, B, C, t, bm, s);
+    }
+    return TLIB_EDTYPE;
+}
+
+int launch_axpby_tile(int in_dtype, int out_dtype, double alpha, const void* A, double beta, const void* B,
+                      void* C, const EwTile& t, int b_mode, hipStream_t s) {
+    if (b_mode < 0 || b_mode > 2) return TLIB_EINVAL;
+    switch (in_dtype) {
+        case TLIB_F64: return axpby_tile_out<double>(out_dtype, alpha, A, beta, B, C, t, b_mode, s);
+        case TLIB_F32: return axpby_tile_out<float>(out_dtype, alpha, A, beta, B, C, t, b_mode, s);
+        case TLIB_BF16: return axpby_tile_out<bf16_t>(out_dtype, alpha, A, beta, B, C, t, b_mode, s);
+        case TLIB_F16: return axpby_tile_out<f16_t>(out_dtype, alpha, A, beta, B, C, t, b_mode, s);
+    }
+    return TLIB_EDTYPE;
+}
+
 }  // namespace tlib

@@ -279,3 +279,33 @@ def test_ttm2_plans_and_errors():
         Vb = _d((32, n), _lib.BF16, ptr=FAKE * 3)
         assert call(Ab, Ub, 1, Vb, 2, C) == _lib.EDTYPE
         assert call(A, U, 1, V, 2, _d((32, 32, n, n), _lib.F32, ptr=FAKE + 64)) == _lib.EALIAS
+
+
+def test_ewise_regimes():
+    """Entrywise ops: the LDS-tiled relayout when C's fastest dim is not A's,
+    the plain kernel otherwise; B read with A's tile or along C's lines."""
+    L = _lib.lib()
+    with Plan():
+        A = _d((90, 90, 90), _lib.F32, layout=(3, 2, 1))
+        Ad = _d((90, 90, 90), _lib.F32, ptr=FAKE * 4)
+        C = _d((90, 90, 90), _lib.F32, ptr=FAKE * 2)
+        B = _d((90, 90, 90), _lib.F32, layout=(3, 2, 1), ptr=FAKE * 3)
+        assert L.tlib_scale(2.0, ctypes.byref(A), ctypes.byref(C), None) == 0
+        assert _plan().startswith("scale ewise tile") and "x=90 y=90 rest=90 b=0" in _plan()
+        assert L.tlib_add(1.0, ctypes.byref(A), 1.0, ctypes.byref(B), ctypes.byref(C), None) == 0
+        assert "ewise tile" in _plan() and "b=2" in _plan()
+        assert L.tlib_add(1.0, ctypes.byref(A), 1.0, ctypes.byref(Ad), ctypes.byref(C), None) == 0
+        assert "ewise tile" in _plan() and "b=1" in _plan()
+        # same layouts: one flat stream
+        assert L.tlib_add(1.0, ctypes.byref(Ad), 1.0, ctypes.byref(Ad), ctypes.byref(C), None) == 0
+        assert "ewise" in _plan() and "tile" not in _plan() and _plan().endswith("flat")
+        # transpose of a matrix
+        M = _d((300, 200), _lib.F64)
+        Mt = _d((200, 300), _lib.F64, ptr=FAKE * 2)
+        assert L.tlib_transpose(ctypes.byref(M), _lib.i32_array((2, 1)), ctypes.byref(Mt), None) == 0
+        assert _plan().startswith("transpose ewise tile") and "x=200 y=300 rest=1" in _plan()
+        # a short fastest dim (8 < 16) keeps the plain kernel
+        S = _d((8, 500), _lib.F64, layout=(2, 1))
+        Sc = _d((8, 500), _lib.F64, ptr=FAKE * 2)
+        assert L.tlib_scale(1.0, ctypes.byref(S), ctypes.byref(Sc), None) == 0
+        assert "tile" not in _plan()
