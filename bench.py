@@ -461,16 +461,21 @@ def views_bench(args):
     reps = max(1, args.steps)
 
     def timed(fn):
+        # median over 5 batches of `reps` calls: a host-side stall (the GPU
+        # idles until the next launch arrives) lands in one batch only
         fn()
         torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps * 1e-3
+        ts = []
+        for _ in range(5):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / reps * 1e-3)
+        return sorted(ts)[2]
 
     out = {}
     totals = {}
@@ -523,7 +528,7 @@ def views_bench(args):
         "metric": METRIC,
         "value": round(value, 1),
         "unit": "GB/s (mean over views and dtypes of useful bytes / time for TTV, TTM, norm, inner, add)",
-        "n_gpus": 1, "steps": reps, "warmup": 1,
+        "n_gpus": 1, "steps": reps, "warmup": 1, "timing": "median of 5 batches of `steps` calls per op",
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32, f64", "data": "synthetic: U[0,1) views of 90^4 tensors (seeded)",
         "config": {"workload": "strided views (ranges with steps) of order-4 90^4 tensors"},

@@ -68,48 +68,68 @@ __global__ __launch_bounds__(DOT_BLOCK) void dot_pass1(const TI* A, const TI* B,
     if (tid == 0) part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
-// Views whose dims do not merge: rows along the innermost dim (g.n[0]
-// elements), each row's offsets decoded once over the other dims, G lanes per
-// row streaming it; workgroup b owns rows [b rpb, (b+1) rpb).  The partition
-// and every summation order are fixed.
-template <typename TI>
-__global__ __launch_bounds__(DOT_BLOCK) void dot_rows(const TI* A, const TI* B, GDims g, int64_t rows, int64_t rpb,
-                                                      int G, double* part) {
+// Views whose dims do not merge: rows along the innermost dim (n0 elements,
+// stride sa / sb), each row's offsets decoded (32-bit fast divide) over the
+// other dims.  G lanes per row take J elements each per pass; a group keeps RU
+// rows in flight, so that a lane has RU*J loads outstanding.  Workgroup b owns
+// rows [b rpb, (b+1) rpb).  The partition and every summation order are fixed.
+struct DotRowDec {
+    int nr = 0;
+    uint32_t n[MAXP] = {};
+    FastDiv fd[MAXP];
+    int64_t s0[MAXP] = {}, s1[MAXP] = {};
+};
+
+__device__ uint64_t g_dot_zero[2];
+
+template <typename TI, int J, int RU>
+__global__ __launch_bounds__(DOT_BLOCK) void dot_rows(const TI* A, const TI* B, int64_t n0, int64_t sa, int64_t sb,
+                                                      DotRowDec R, uint32_t rows, uint32_t rpb, int G,
+                                                      double* part) {
     const int tid = threadIdx.x;
     const int gi = tid / G, l = tid % G, per = DOT_BLOCK / G;
-    const int64_t r0 = int64_t(blockIdx.x) * rpb, r1 = min(rows, r0 + rpb);
-    const int64_t n0 = g.n[0], sa = g.s[0][0], sb = g.s[1][0];
+    const uint32_t r0 = blockIdx.x * rpb, r1 = min(rows, r0 + rpb);
+    const TI* zs = reinterpret_cast<const TI*>(g_dot_zero);
     double acc = 0.0;
-    for (int64_t r = r0 + gi; r < r1; r += per) {
-        int64_t lin = r, oa = 0, ob = 0;
-        for (int d = 1; d < g.nd; ++d) {
-            const int64_t q = d == g.nd - 1 ? 0 : lin / g.n[d];
-            const int64_t rr = lin - q * g.n[d];
-            oa += rr * g.s[0][d];
-            ob += rr * g.s[1][d];
-            lin = q;
-        }
-        const TI* a = A + oa;
-        const TI* b = B ? B + ob : nullptr;
-        int64_t c = l;
-        for (; c + 3 * G < n0; c += 4 * G) {
-            const double a0 = to_f64(a[c * sa]), a1 = to_f64(a[(c + G) * sa]);
-            const double a2 = to_f64(a[(c + 2 * G) * sa]), a3 = to_f64(a[(c + 3 * G) * sa]);
-            if (b) {
-                acc += a0 * to_f64(b[c * sb]);
-                acc += a1 * to_f64(b[(c + G) * sb]);
-                acc += a2 * to_f64(b[(c + 2 * G) * sb]);
-                acc += a3 * to_f64(b[(c + 3 * G) * sb]);
-            } else {
-                acc += a0 * a0;
-                acc += a1 * a1;
-                acc += a2 * a2;
-                acc += a3 * a3;
+    for (uint32_t r = r0 + uint32_t(gi) * RU; r < r1; r += uint32_t(per) * RU) {
+        const TI* a[RU];
+        const TI* b[RU];
+        bool lv[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            lv[u] = r + u < r1;
+            uint32_t lin = lv[u] ? r + u : r;
+            int64_t oa = 0, ob = 0;
+#pragma unroll
+            for (int d = 0; d < MAXP; ++d) {
+                if (d >= R.nr) break;
+                const uint32_t q = d == R.nr - 1 ? 0u : fdiv(lin, R.fd[d]);
+                const int64_t i = int64_t(lin - q * R.n[d]);
+                oa += i * R.s0[d];
+                ob += i * R.s1[d];
+                lin = q;
             }
+            a[u] = A + oa;
+            b[u] = B ? B + ob : zs;
         }
-        for (; c < n0; c += G) {
-            const double x = to_f64(a[c * sa]);
-            acc += x * (b ? to_f64(b[c * sb]) : x);
+        for (int64_t c = l; c < n0; c += int64_t(J) * G) {
+            TI xa[RU][J], xb[RU][J];
+#pragma unroll
+            for (int u = 0; u < RU; ++u)
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    const int64_t cj = c + int64_t(j) * G;
+                    const bool in = lv[u] && cj < n0;
+                    xa[u][j] = *(in ? a[u] + cj * sa : zs);
+                    if (B) xb[u][j] = *(in ? b[u] + cj * sb : zs);
+                }
+#pragma unroll
+            for (int u = 0; u < RU; ++u)
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    const double x = to_f64(xa[u][j]);
+                    acc += x * (B ? to_f64(xb[u][j]) : x);
+                }
         }
     }
     acc = warp_sum(acc, 64);
@@ -137,13 +157,28 @@ template <typename TI>
 static int dot_launch(const void* A, const void* B, const GDims& g, double* out, bool sq, void* ws,
                       hipStream_t s) {
     int np = dot_partials(g.total);
-    if (g.nd >= 2) {
+    if (g.nd >= 2 && g.total / g.n[0] < (int64_t(1) << 31)) {
         const int64_t rows = g.total / g.n[0];
         const int G = g.n[0] >= 256 ? 64 : g.n[0] >= 64 ? 32 : g.n[0] >= 16 ? 16 : 8;
         const int64_t rpb = (rows + np - 1) / np;
         np = int((rows + rpb - 1) / rpb);
-        hipLaunchKernelGGL((dot_rows<TI>), dim3(np), dim3(DOT_BLOCK), 0, s, (const TI*)A, (const TI*)B, g, rows, rpb,
-                           G, (double*)ws);
+        DotRowDec R;
+        R.nr = g.nd - 1;
+        for (int d = 1; d < g.nd; ++d) {
+            R.n[d - 1] = uint32_t(g.n[d]);
+            R.fd[d - 1] = make_fastdiv(uint32_t(g.n[d]));
+            R.s0[d - 1] = g.s[0][d];
+            R.s1[d - 1] = g.s[1][d];
+        }
+        const int64_t J = std::min<int64_t>(4, (g.n[0] + G - 1) / G);
+#define TLIB_DOT_ROWS(JJ, RR)                                                                                   \
+    hipLaunchKernelGGL((dot_rows<TI, JJ, RR>), dim3(np), dim3(DOT_BLOCK), 0, s, (const TI*)A, (const TI*)B, g.n[0], \
+                       g.s[0][0], g.s[1][0], R, uint32_t(rows), uint32_t(rpb), G, (double*)ws)
+        if (J == 1) TLIB_DOT_ROWS(1, 8);
+        else if (J == 2) TLIB_DOT_ROWS(2, 8);
+        else if (J == 3) TLIB_DOT_ROWS(3, 4);
+        else TLIB_DOT_ROWS(4, 4);
+#undef TLIB_DOT_ROWS
     } else {
         const int64_t chunk = (g.total + np - 1) / np;
         hipLaunchKernelGGL((dot_pass1<TI>), dim3(np), dim3(DOT_BLOCK), 0, s, (const TI*)A, (const TI*)B, g, chunk,

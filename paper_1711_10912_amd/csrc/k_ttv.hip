@@ -207,37 +207,57 @@ __global__ __launch_bounds__(256) void ttv_slab_kernel(TtvParams P, int slabs, i
     }
 }
 
-template <typename TI>
+__device__ uint64_t g_fiber_zero[2];
+
+// G lanes per output fiber, J elements per lane per pass, RU outputs per group
+// in flight (RU*J loads outstanding per lane).  Each lane sums its elements in
+// k order; the group then reduces by shuffles.
+template <typename TI, int J, int RU>
 __global__ __launch_bounds__(256) void ttv_fiber_kernel(TtvParams P, Grp go, int G, int64_t outs) {
     using TA = typename AccOf<TI>::type;
     const TI* A = (const TI*)P.A;
     const TI* b = (const TI*)P.b;
     TA* C = (TA*)P.C;
+    const TI* zs = reinterpret_cast<const TI*>(g_fiber_zero);
     const int g = threadIdx.x % G;
-    const int64_t per = 256 / G;
+    const int64_t per = 256 / G * RU;
     // the outer loop runs the same rounds for every thread of the block
-    // (outputs past the end take a zero-length fiber), so every shuffle sees
-    // all lanes of its group
+    // (outputs past the end take no elements), so every shuffle sees all
+    // lanes of its group
     for (int64_t o0 = int64_t(blockIdx.x) * per; o0 < outs; o0 += int64_t(gridDim.x) * per) {
-        const int64_t o = o0 + threadIdx.x / G;
-        const bool ok = o < outs;
-        int64_t oa, oc;
-        grp_decode(uint32_t(ok ? o : 0), go, oa, oc);
-        const TI* a = A + oa;
-        const int64_t nk = ok ? P.n_k : 0;
-        TA acc = TA(0);
-        int64_t k = g;
-        for (; k + 3 * G < nk; k += 4 * G) {
-            const TA x0 = to_acc(a[k * P.sA_k]), x1 = to_acc(a[(k + G) * P.sA_k]);
-            const TA x2 = to_acc(a[(k + 2 * G) * P.sA_k]), x3 = to_acc(a[(k + 3 * G) * P.sA_k]);
-            acc += x0 * to_acc(b[k * P.sb]);
-            acc += x1 * to_acc(b[(k + G) * P.sb]);
-            acc += x2 * to_acc(b[(k + 2 * G) * P.sb]);
-            acc += x3 * to_acc(b[(k + 3 * G) * P.sb]);
+        const int64_t ob = o0 + int64_t(threadIdx.x / G) * RU;
+        const TI* a[RU];
+        int64_t oc[RU];
+        bool ok[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            ok[u] = ob + u < outs;
+            int64_t oa;
+            grp_decode(uint32_t(ok[u] ? ob + u : 0), go, oa, oc[u]);
+            a[u] = A + oa;
         }
-        for (; k < nk; k += G) acc += to_acc(a[k * P.sA_k]) * to_acc(b[k * P.sb]);
-        acc = warp_sum(acc, G);
-        if (ok && g == 0) C[oc] = acc;
+        TA acc[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) acc[u] = TA(0);
+        for (int64_t k = g; k < P.n_k; k += int64_t(J) * G) {
+            TI xa[RU][J], xb[J];
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const int64_t kj = k + int64_t(j) * G;
+                xb[j] = *(kj < P.n_k ? b + kj * P.sb : zs);
+#pragma unroll
+                for (int u = 0; u < RU; ++u) xa[u][j] = *(ok[u] && kj < P.n_k ? a[u] + kj * P.sA_k : zs);
+            }
+#pragma unroll
+            for (int u = 0; u < RU; ++u)
+#pragma unroll
+                for (int j = 0; j < J; ++j) acc[u] += to_acc(xa[u][j]) * to_acc(xb[j]);
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const TA v = warp_sum(acc[u], G);
+            if (ok[u] && g == 0) C[oc[u]] = v;
+        }
     }
 }
 
@@ -318,9 +338,18 @@ int launch_ttv_slab(int dtype, const TtvParams& p, int slabs, int kc, hipStream_
 template <typename TI>
 static int fiber_launch(const TtvParams& p, const Grp& go, int G, hipStream_t s) {
     const int64_t outs = go.total;
-    const int64_t per = 256 / G;
+    const int64_t J = std::min<int64_t>(4, (p.n_k + G - 1) / G);
+    const int RU = J <= 2 ? 8 : 4;
+    const int64_t per = 256 / G * RU;
     const unsigned blocks = unsigned(std::max<int64_t>(1, std::min<int64_t>((outs + per - 1) / per, 8192)));
-    hipLaunchKernelGGL((ttv_fiber_kernel<TI>), dim3(blocks), dim3(256), 0, s, p, go, G, outs);
+    if (J == 1)
+        hipLaunchKernelGGL((ttv_fiber_kernel<TI, 1, 8>), dim3(blocks), dim3(256), 0, s, p, go, G, outs);
+    else if (J == 2)
+        hipLaunchKernelGGL((ttv_fiber_kernel<TI, 2, 8>), dim3(blocks), dim3(256), 0, s, p, go, G, outs);
+    else if (J == 3)
+        hipLaunchKernelGGL((ttv_fiber_kernel<TI, 3, 4>), dim3(blocks), dim3(256), 0, s, p, go, G, outs);
+    else
+        hipLaunchKernelGGL((ttv_fiber_kernel<TI, 4, 4>), dim3(blocks), dim3(256), 0, s, p, go, G, outs);
     return hipGetLastError() == hipSuccess ? TLIB_OK : TLIB_EHIP;
 }
 

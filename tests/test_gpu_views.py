@@ -83,3 +83,33 @@ def test_views_ttm_inner_norm(T, dtype):
         ref = oracle.inner(Xr, oracle.materialize(round_to(Y, dtype)))
         scale = oracle.inner(np.abs(Xr), np.abs(oracle.materialize(round_to(Y, dtype))))
         assert abs(got - ref) <= 1e-12 * scale, name
+
+
+@pytest.mark.parametrize("n0", [5, 20, 40, 90, 150, 300, 1100])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_views_rows_and_fibers_every_width(T, n0, dtype):
+    """Row lengths that take every lane count and per-lane width of the row-wise
+    inner/norm and of the fiber TTV, with ragged row counts."""
+    import torch
+    from _util import torch_dtype
+    g = synth.rng(62, _seed(n0, dtype))
+    m, k = 13, 7
+    A = T.empty((n0, m + 2, k), None, torch_dtype(dtype), "cuda")[:, :m]
+    X = synth.uniform(tuple(A.shape), g)
+    A.copy_(torch.from_numpy(X).to(A.dtype).cuda())
+    Xr = oracle.materialize(round_to(X, dtype))
+    got = float(T.norm(A).item())
+    assert abs(got - oracle.norm(Xr)) <= 1e-12 * oracle.norm(Xr)
+    Y = synth.uniform(tuple(A.shape), g)
+    B2 = T.empty((n0, m + 5, k), [2, 1, 3], A.dtype, "cuda")[:, 2:m + 2]
+    B2.copy_(torch.from_numpy(Y).to(A.dtype).cuda())
+    Yr = oracle.materialize(round_to(Y, dtype))
+    got = float(T.inner(A, B2).item())
+    assert abs(got - oracle.inner(Xr, Yr)) <= 1e-12 * oracle.inner(np.abs(Xr), np.abs(Yr))
+    b = synth.uniform((n0,), g)
+    bt = torch.from_numpy(b).to(A.dtype).cuda()
+    C = T.empty((m, k), [2, 1], torch.float64 if dtype == "f64" else torch.float32, "cuda")
+    assert T.plan(T.ttv, A, bt, 1, out=C).split(" ")[1] == "fiber"
+    T.ttv(A, bt, 1, out=C)
+    tol = TOL[dtype] if dtype != "bf16" else 1e-5
+    assert_close(to_np(C), oracle.ttv(Xr, round_to(b, dtype), 1), tol, "fiber n0=%d" % n0)
