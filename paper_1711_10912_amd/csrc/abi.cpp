@@ -587,6 +587,24 @@ static int run_gemm(int dtype, const void* X, const void* Y, void* C, Dim* dm, i
                 else if (dtype == TLIB_F32 && P.syk % 2 == 0 && (uintptr_t(Y) % 8) == 0) P.y_vec = 2;
             }
         }
+        {
+            // 16-bit operands whose K has a first dim of unit stride (extent a
+            // multiple of 8) load 16-byte groups of 8 consecutive k; every
+            // other stride and the base keep the groups 16-byte aligned.
+            P.kvec = 0;
+            if ((dtype == TLIB_BF16 || dtype == TLIB_F16) && ndk >= 1 && dk[0].n % 8 == 0) {
+                auto groups_ok = [&](int o, const void* base, const Dim* d, int nd) {
+                    if (dk[0].s[o] != 1 || (uintptr_t(base) % 16) != 0) return false;
+                    for (int i = 1; i < ndk; ++i)
+                        if (dk[i].s[o] % 8 != 0) return false;
+                    for (int i = 0; i < nd; ++i)
+                        if (d[i].s[0] % 8 != 0) return false;
+                    return true;
+                };
+                if (groups_ok(0, X, dm, ndm)) P.kvec |= 1;
+                if (groups_ok(1, Y, dn, ndn)) P.kvec |= 2;
+            }
+        }
         // FP64 accumulators are twice as wide: keep a wave's tile at 64x32 so
         // that two waves fit per SIMD.
         const bool wide_acc = dtype == TLIB_F64;
@@ -622,9 +640,9 @@ static int run_gemm(int dtype, const void* X, const void* Y, void* C, Dim* dm, i
                                         size_t(esize(acc_dtype(dtype)))
                                   : 0;
         plan_note("%s gemm dtype=%s M=%lld N=%lld K=%lld dims=(%d,%d,%d) tile=%dx%d kfast=(%d,%d) "
-                  "cvec=%d yvec=%d ksplit=%d tiles=%lld",
+                  "cvec=%d yvec=%d kvec=%d ksplit=%d tiles=%lld",
                   op, dname(dtype), (long long)M, (long long)N, (long long)K, ndm, ndn, ndk, ts.bm,
-                  ts.bn, P.x_kfast, P.y_kfast, P.c_vec, P.y_vec, P.ksplit, (long long)nt);
+                  ts.bn, P.x_kfast, P.y_kfast, P.c_vec, P.y_vec, P.kvec, P.ksplit, (long long)nt);
         if (g_plan_only) return TLIB_OK;
         if (P.ksplit > 1) {
             P.part = workspace(s, wsb);

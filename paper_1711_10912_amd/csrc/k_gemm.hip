@@ -109,7 +109,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
     constexpr int EX = BM * BK / 256;  // X elements per thread per K slice
     constexpr int EY = BN * BK / 256;
     static_assert(EX >= 1 && EY >= 1, "tile too small");
-    constexpr bool YV = YW > 0;
+    // FP32/FP64: YW > 0 = Y as vectors along N.  16-bit: YW bit 0 / bit 1 =
+    // X / Y loaded as 16-byte groups of 8 consecutive k (see fetch).
+    constexpr bool YV = !WIDE && YW > 0;
+    constexpr bool XKV = WIDE && (YW & 1) != 0;
+    constexpr bool YKV = WIDE && (YW & 2) != 0;
+    constexpr int KG = BK / 8;                     // 8-element k groups per slice
+    constexpr int NXV = BM * KG, NYV = BN * KG;    // k groups per X / Y slice
+    constexpr int EXV = (NXV + 255) / 256, EYK = (NYV + 255) / 256;
     constexpr int VY = YV ? YW : 1;
     constexpr int CG = BN / VY;                   // column groups of a Y slice
     constexpr int RS = YV ? 256 / CG : 1;         // rows of the slice per pass
@@ -188,8 +195,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
         else { nn = e % BN; kk = e / BN; }
     };
 
-    RT xr[EX], yr[YV ? 1 : EY];
+    RT xr[XKV ? 1 : EX], yr[(YV || YKV) ? 1 : EY];
     yv_t yvr[EYV];
+    u4_t xg[XKV ? EXV : 1], yg[YKV ? EYK : 1];
     // YV: this thread's column group and first row, the group's offset and
     // whether every thread of the wave has VY consecutive, aligned columns
     const int ycg = tid % CG, yrow = tid / CG;
@@ -197,15 +205,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
     bool wvec = false;
     int k0n = 0;  // first k of the slice being fetched
     const TI* zsrc = reinterpret_cast<const TI*>(g_gemm_zero);
+    // 16-bit k groups: slot e = tid + 256 j is group e % KG of row / column
+    // e / KG.  The host enables them only where K's first dim has unit stride
+    // in the operand and a multiple of 8 extent and every other stride keeps
+    // the groups 16-byte aligned, so the group starting at a valid k is
+    // wholly inside the slice's K range and contiguous in memory.
     auto fetch = [&](int slot) {
+        if constexpr (XKV) {
 #pragma unroll
-        for (int j = 0; j < EX; ++j) {
-            int mm, kk;
-            xslot(j, mm, kk);
-            const int64_t a = xrow[mm], b = kx[slot][kk];
-            xr[j] = (a >= 0 && b >= 0) ? raw_load(X + a + b) : RT(0);
+            for (int j = 0; j < EXV; ++j) {
+                const int e = tid + j * 256;
+                const int mm = min(e / KG, BM - 1), kv = e % KG;
+                const int64_t a = e < NXV ? xrow[mm] : -1, b = kx[slot][kv * 8];
+                xg[j] = *reinterpret_cast<const u4_t*>((a >= 0 && b >= 0) ? X + (a + b) : zsrc);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < EX; ++j) {
+                int mm, kk;
+                xslot(j, mm, kk);
+                const int64_t a = xrow[mm], b = kx[slot][kk];
+                xr[j] = (a >= 0 && b >= 0) ? raw_load(X + a + b) : RT(0);
+            }
         }
-        if constexpr (YV) {
+        if constexpr (YKV) {
+#pragma unroll
+            for (int j = 0; j < EYK; ++j) {
+                const int e = tid + j * 256;
+                const int nn = min(e / KG, BN - 1), kv = e % KG;
+                const int64_t a = e < NYV ? ycol[nn] : -1, b = ky[slot][kv * 8];
+                yg[j] = *reinterpret_cast<const u4_t*>((a >= 0 && b >= 0) ? Y + (a + b) : zsrc);
+            }
+        } else if constexpr (YV) {
             // the choice is per wave (wvec is uniform), so only one of the two
             // load sequences runs and no load waits for the other's registers
             if (wvec) {
@@ -236,14 +267,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
         }
     };
     auto stash = [&]() {
+        if constexpr (XKV) {
 #pragma unroll
-        for (int j = 0; j < EX; ++j) {
-            int mm, kk;
-            xslot(j, mm, kk);
-            if constexpr (WIDE) Xs[mm * PX + kk] = xr[j];
-            else Xs[kk * PX + mm] = xr[j];
+            for (int j = 0; j < EXV; ++j) {
+                const int e = tid + j * 256;
+                if (e < NXV) *reinterpret_cast<u4_t*>(&Xs[(e / KG) * PX + (e % KG) * 8]) = xg[j];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < EX; ++j) {
+                int mm, kk;
+                xslot(j, mm, kk);
+                if constexpr (WIDE) Xs[mm * PX + kk] = xr[j];
+                else Xs[kk * PX + mm] = xr[j];
+            }
         }
-        if constexpr (YV) {
+        if constexpr (YKV) {
+#pragma unroll
+            for (int j = 0; j < EYK; ++j) {
+                const int e = tid + j * 256;
+                if (e < NYV) *reinterpret_cast<u4_t*>(&Ys[(e / KG) * PY + (e % KG) * 8]) = yg[j];
+            }
+        } else if constexpr (YV) {
 #pragma unroll
             for (int j = 0; j < EYV; ++j) *reinterpret_cast<yv_t*>(&Ys[(yrow + RS * j) * PY + ycg * VY]) = yvr[j];
         } else {
@@ -428,7 +473,12 @@ static int gemm_launch(const GemmParams& p, hipStream_t s) {
         else if (p.y_vec == 2) hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 2>), grid, dim3(256), 0, s, p);
         else hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 0>), grid, dim3(256), 0, s, p);
     } else {
-        hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 0>), grid, dim3(256), 0, s, p);
+        switch (p.kvec) {
+            case 1: hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 1>), grid, dim3(256), 0, s, p); break;
+            case 2: hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 2>), grid, dim3(256), 0, s, p); break;
+            case 3: hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 3>), grid, dim3(256), 0, s, p); break;
+            default: hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 0>), grid, dim3(256), 0, s, p);
+        }
     }
     if (hipGetLastError() != hipSuccess) return TLIB_EHIP;
     if (p.ksplit > 1) {
