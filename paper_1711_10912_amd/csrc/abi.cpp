@@ -355,14 +355,27 @@ static int run_ttv(const Ten& a, const Ten& b, int mi, const Ten& c, hipStream_t
             int64_t maxk = std::max<int64_t>(1, P.n_k / 32);
             ks = int(std::min<int64_t>(std::min<int64_t>(want, maxk), 64));
         }
+        // short k and enough units: one wave per (lo tile, hi) unit with all
+        // rows in flight (at most 256 bytes of rows per lane)
+        int kr = 0;
+        if (ks == 1 && nb >= 4096)
+            for (int c : {8, 16, 32, 64})
+                if (P.n_k <= c && int64_t(c) * vec * es <= 256) {
+                    kr = c;
+                    break;
+                }
         void* ws = nullptr;
         size_t wsb = ks > 1 ? size_t(ks) * size_t(outs) * size_t(esize(acc_dtype(a.dtype))) : 0;
         plan_note("ttv col dtype=%s n_lo=%lld n_k=%lld n_hi=%lld sA=(%lld,%lld,%lld) sC=(%lld,%lld) "
-                  "hidims=%d vec=%d ksplit=%d blocks=%lld",
+                  "hidims=%d vec=%d ksplit=%d kr=%d blocks=%lld",
                   dname(a.dtype), (long long)P.n_lo, (long long)P.n_k, (long long)P.n_hi,
                   (long long)P.sA_lo, (long long)P.sA_k, (long long)P.sA_hi, (long long)P.sC_lo,
-                  (long long)P.sC_hi, P.gh.nd, vec, ks, (long long)(nb * ks));
+                  (long long)P.sC_hi, P.gh.nd, vec, ks, kr, (long long)(kr ? (nb + 3) / 4 : nb * ks));
         if (g_plan_only) return TLIB_OK;
+        if (kr) {
+            int rc = launch_ttv_colw(a.dtype, P, vec, kr, s);
+            return rc ? fail(rc, "ttv: launch failed") : TLIB_OK;
+        }
         if (ks > 1) {
             ws = workspace(s, wsb);
             if (!ws) return fail(TLIB_ENOMEM, "ttv: workspace of %zu bytes", wsb);

@@ -243,6 +243,9 @@ TileShape tile_shape(int t);
 
 // ------------------------------------------------------------------ launchers (k_*.hip)
 // Each returns TLIB_OK or TLIB_EHIP.
+// Col kernel with one wave per (lo tile, hi) unit and kr >= n_k rows in flight
+// (kr in {8, 16, 32, 64}, kr * vec * element size <= 256 bytes).
+int launch_ttv_colw(int dtype, const TtvParams& p, int vec, int kr, hipStream_t s);
 int launch_ttv_col(int dtype, const TtvParams& p, int vec, int ksplit, void* ws, hipStream_t s);
 int launch_ttv_slab(int dtype, const TtvParams& p, int slabs, int kc, hipStream_t s);
 int launch_ttv_generic(int dtype, const TtvParams& p, const GDims& out, hipStream_t s);

@@ -8,6 +8,8 @@
 //         order; optional grid split over k with a second summing pass.  The
 //         hi index is decoded over up to four dims, so views whose outer dims
 //         do not merge (ranges, steps) stay on this kernel.
+//         With a short k (and no grid split) each wave owns a whole
+//         (lo tile, hi) unit instead and keeps all of its rows in flight.
 //   slab  (n_lo < 32 and the (lo,k) slabs contiguous): a workgroup copies whole
 //         contiguous slabs into LDS with coalesced loads, then groups of G lanes
 //         reduce each output's k-fiber out of LDS with a shuffle tree.
@@ -108,6 +110,48 @@ __global__ __launch_bounds__(256) void ttv_col_kernel(TtvParams P, int64_t lo_ti
             else C[lo * P.sC_lo + hC] = s;
         }
     }
+}
+
+// Col kernel for a short contraction (n_k <= KR): each wave owns one
+// (lo tile, hi) unit and keeps all of its k rows in flight at once (rows past
+// n_k load from a zero word), so a unit costs one memory round trip and no
+// workgroup barrier.  Each lane adds its rows in k order.
+__device__ __align__(16) double g_ttv_zero[2] = {0.0, 0.0};
+
+template <typename TI, int VEC, int KR>
+__global__ __launch_bounds__(256) void ttv_colw_kernel(TtvParams P, int64_t lo_tiles, int64_t units) {
+    using TA = typename AccOf<TI>::type;
+    const int lane = threadIdx.x & 63;
+    const int64_t u = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (u >= units) return;
+    const int64_t hi = u / lo_tiles, lt = u - hi * lo_tiles;
+    const int64_t lo0 = (lt * 64 + lane) * VEC;
+    if (lo0 >= P.n_lo) return;
+    int64_t hA, hC;
+    grp_decode(uint32_t(hi), P.gh, hA, hC);
+    const TI* Ap = (const TI*)P.A + hA + lo0 * P.sA_lo;
+    const TI* b = (const TI*)P.b;
+    const TI* zs = reinterpret_cast<const TI*>(g_ttv_zero);
+    TA acc[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] = TA(0);
+    for (int64_t k0 = 0; k0 < P.n_k; k0 += KR) {
+        TA x[KR][VEC], bk[KR];
+#pragma unroll
+        for (int r = 0; r < KR; ++r) {
+            const int64_t k = k0 + r;
+            const bool in = k < P.n_k;
+            load_vec<TI, VEC>(in ? Ap + k * P.sA_k : zs, x[r]);
+            bk[r] = to_acc(*(in ? b + k * P.sb : zs));
+        }
+#pragma unroll
+        for (int r = 0; r < KR; ++r)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[v] += x[r][v] * bk[r];
+    }
+    TA* C = (TA*)P.C;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) C[(lo0 + v) * P.sC_lo + hC] = acc[v];
 }
 
 template <typename TA>
@@ -297,6 +341,31 @@ static int col_launch(const TtvParams& p, int ksplit, void* ws, hipStream_t s) {
     return TLIB_OK;
 }
 
+template <typename TI, int VEC, int KR>
+static int colw_launch(const TtvParams& p, hipStream_t s) {
+    if constexpr (KR * VEC * int(sizeof(TI)) > 256) {
+        return TLIB_EINVAL;
+    } else {
+        const int64_t lo_tiles = (p.n_lo + 64 * VEC - 1) / (64 * VEC);
+        const int64_t units = lo_tiles * p.n_hi;
+        const int64_t blocks = (units + 3) / 4;
+        hipLaunchKernelGGL((ttv_colw_kernel<TI, VEC, KR>), dim3(unsigned(blocks)), dim3(256), 0, s, p, lo_tiles,
+                           units);
+        return hipGetLastError() == hipSuccess ? TLIB_OK : TLIB_EHIP;
+    }
+}
+
+template <typename TI, int VEC>
+static int colw_kr(const TtvParams& p, int kr, hipStream_t s) {
+    switch (kr) {
+        case 8: return colw_launch<TI, VEC, 8>(p, s);
+        case 16: return colw_launch<TI, VEC, 16>(p, s);
+        case 32: return colw_launch<TI, VEC, 32>(p, s);
+        case 64: return colw_launch<TI, VEC, 64>(p, s);
+    }
+    return TLIB_EINVAL;
+}
+
 template <typename TI>
 static int col_dispatch(const TtvParams& p, int vec, int ksplit, void* ws, hipStream_t s) {
     constexpr int MAXV = 16 / sizeof(TI);
@@ -304,6 +373,25 @@ static int col_dispatch(const TtvParams& p, int vec, int ksplit, void* ws, hipSt
     if (vec >= 4 && MAXV >= 4) return col_launch<TI, (MAXV >= 4 ? 4 : 1)>(p, ksplit, ws, s);
     if (vec >= 2) return col_launch<TI, 2>(p, ksplit, ws, s);
     return col_launch<TI, 1>(p, ksplit, ws, s);
+}
+
+template <typename TI>
+static int colw_dispatch(const TtvParams& p, int vec, int kr, hipStream_t s) {
+    constexpr int MAXV = 16 / sizeof(TI);
+    if (vec >= 8 && MAXV >= 8) return colw_kr<TI, (MAXV >= 8 ? 8 : 1)>(p, kr, s);
+    if (vec >= 4 && MAXV >= 4) return colw_kr<TI, (MAXV >= 4 ? 4 : 1)>(p, kr, s);
+    if (vec >= 2) return colw_kr<TI, 2>(p, kr, s);
+    return colw_kr<TI, 1>(p, kr, s);
+}
+
+int launch_ttv_colw(int dtype, const TtvParams& p, int vec, int kr, hipStream_t s) {
+    switch (dtype) {
+        case TLIB_F64: return colw_dispatch<double>(p, vec, kr, s);
+        case TLIB_F32: return colw_dispatch<float>(p, vec, kr, s);
+        case TLIB_BF16: return colw_dispatch<bf16_t>(p, vec, kr, s);
+        case TLIB_F16: return colw_dispatch<f16_t>(p, vec, kr, s);
+    }
+    return TLIB_EDTYPE;
 }
 
 int launch_ttv_col(int dtype, const TtvParams& p, int vec, int ksplit, void* ws, hipStream_t s) {
