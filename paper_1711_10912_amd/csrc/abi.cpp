@@ -383,7 +383,11 @@ static int run_ttv(const Ten& a, const Ten& b, int mi, const Ten& c, hipStream_t
         int rc = launch_ttv_col(a.dtype, P, vec, ks, ws, s);
         return rc ? fail(rc, "ttv: launch failed") : TLIB_OK;
     }
-    const bool slab_ok = fast && (P.n_lo == 1 || P.sA_lo == 1) && (P.n_k == 1 || P.sA_k == P.n_lo) &&
+    // n_lo == 1 with k of unit stride and n_k >= 32: every output is one
+    // contiguous fiber, which the fiber kernel streams without staging
+    // (below); shorter fibers fill its lane groups poorly and stay on slabs
+    const bool row_fibers = fast && P.n_lo == 1 && P.sA_k == 1 && P.n_k >= 32;
+    const bool slab_ok = fast && !row_fibers && (P.n_lo == 1 || P.sA_lo == 1) && (P.n_k == 1 || P.sA_k == P.n_lo) &&
                          (P.n_hi == 1 || P.sA_hi == P.n_lo * P.n_k);
     if (slab_ok) {
         const int64_t cap = 32768 / es;

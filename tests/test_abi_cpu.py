@@ -72,13 +72,19 @@ def test_ttv_regimes():
         A = _d((n, n, n), ptr=FAKE)
         b = _d((n,), ptr=FAKE * 2)
         C = _d((n, n), ptr=FAKE * 3)
-        assert _ttv(A, b, 1, C) == 0 and _plan().startswith("ttv slab")
+        # mode 1: every output a contiguous fiber of 406
+        assert _ttv(A, b, 1, C) == 0 and _plan().startswith("ttv fiber")
         assert _ttv(A, b, 2, C) == 0 and _plan().startswith("ttv col") and "n_lo=406" in _plan()
         assert _ttv(A, b, 3, C) == 0 and _plan().startswith("ttv col") and "n_lo=164836" in _plan()
         # last-order A: mode 3 is the stride-1 mode
         A = _d((n, n, n), layout=(3, 2, 1))
         Cl = _d((n, n), layout=(2, 1), ptr=FAKE * 3)
-        assert _ttv(A, b, 3, Cl) == 0 and _plan().startswith("ttv slab")
+        assert _ttv(A, b, 3, Cl) == 0 and _plan().startswith("ttv fiber")
+        # short contiguous fibers (20 < 32) are staged through slabs
+        A20 = _d((20,) * 4)
+        b20 = _d((20,), ptr=FAKE * 2)
+        C20 = _d((20,) * 3, ptr=FAKE * 3)
+        assert _ttv(A20, b20, 1, C20) == 0 and _plan().startswith("ttv slab")
         # a C layout that does not follow A's: the dims do not merge, short lo
         # (13 < 32): one fiber per output
         A = _d((13,) * 4)

@@ -2,7 +2,7 @@
 oracle; each case asserts the regime its plan names: the col kernel with one
 wave per (lo tile, hi) unit and all k rows in flight (kr = 8..64, ragged lo,
 vector widths 1/2/4), the col kernel with k split over the waves, with a grid
-split over k, and the slab kernel."""
+split over k, the fiber kernel for contiguous k-fibers and the slab kernel."""
 import zlib
 
 import numpy as np
@@ -34,6 +34,9 @@ REGIMES = [
     ((5000, 33, 40), [3, 2, 1], 2, ["ttv col"]),              # last-order
     ((37, 600, 3), None, 2, ["ttv col", "ksplit="]),
     ((8, 50, 9000), None, 2, ["ttv slab"]),
+    ((300, 4000), None, 1, ["ttv fiber"]),                   # contiguous fibers of 300
+    ((45, 70, 90), [3, 1, 2], 3, ["ttv fiber"]),            # last mode stored first
+    ((20, 9000), None, 1, ["ttv slab"]),                     # short fibers stay on slabs
 ]
 
 
