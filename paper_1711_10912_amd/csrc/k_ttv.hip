@@ -13,9 +13,11 @@
 //   slab  (n_lo < 32 and the (lo,k) slabs contiguous): a workgroup copies whole
 //         contiguous slabs into LDS with coalesced loads, then groups of G lanes
 //         reduce each output's k-fiber out of LDS with a shuffle tree.
-//   fiber (n_lo < 32, slabs not contiguous: views): G lanes per output stream
-//         its k-fiber (coalesced when k has unit stride) and reduce with a
-//         fixed shuffle tree; outputs decoded over up to four dims.
+//   fiber (n_lo < 32, slabs not contiguous: views; and n_lo = 1 with k of
+//         unit stride and n_k >= 32, where every output is one contiguous
+//         fiber): G lanes per output stream its k-fiber (coalesced when k has
+//         unit stride) and reduce with a fixed shuffle tree; outputs decoded
+//         over up to four dims.
 //   generic: one thread per output, any strides.
 // Accumulation is in FP64 for FP64 inputs and in FP32 otherwise.
 #include <algorithm>
