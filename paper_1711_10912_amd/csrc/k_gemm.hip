@@ -27,7 +27,9 @@ typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
 typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
 
-// Source of the loads of vector slots that fall outside Y.
+// Source of the loads that fall outside X or Y: selecting the address rather
+// than the loaded value keeps the loads unconditional, without an exec branch
+// around each one.
 __device__ __align__(16) double g_gemm_zero[2] = {0.0, 0.0};
 
 template <typename TI> struct Mfma;
@@ -225,7 +227,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
                 int mm, kk;
                 xslot(j, mm, kk);
                 const int64_t a = xrow[mm], b = kx[slot][kk];
-                xr[j] = (a >= 0 && b >= 0) ? raw_load(X + a + b) : RT(0);
+                xr[j] = raw_load((a >= 0 && b >= 0) ? X + (a + b) : zsrc);
             }
         }
         if constexpr (YKV) {
@@ -240,11 +242,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
             // the choice is per wave (wvec is uniform), so only one of the two
             // load sequences runs and no load waits for the other's registers
             if (wvec) {
+                // all addresses first, then the loads back to back
+                const yv_t* ap[EYV];
 #pragma unroll
                 for (int j = 0; j < EYV; ++j) {
                     const int k = k0n + yrow + RS * j;
-                    yvr[j] = *reinterpret_cast<const yv_t*>(k < kend ? Y + (ycv + int64_t(k) * P.syk) : zsrc);
+                    ap[j] = reinterpret_cast<const yv_t*>(k < kend ? Y + (ycv + int64_t(k) * P.syk) : zsrc);
                 }
+#pragma unroll
+                for (int j = 0; j < EYV; ++j) yvr[j] = *ap[j];
             } else {
 #pragma unroll
                 for (int j = 0; j < EYV; ++j) {
@@ -262,7 +268,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
                 int nn, kk;
                 yslot(j, nn, kk);
                 const int64_t a = ycol[nn], b = ky[slot][kk];
-                yr[j] = (a >= 0 && b >= 0) ? raw_load(Y + a + b) : RT(0);
+                yr[j] = raw_load((a >= 0 && b >= 0) ? Y + (a + b) : zsrc);
             }
         }
     };
