@@ -197,19 +197,36 @@ __global__ __launch_bounds__(256) void ttm_stream_kernel(TtmParams P) {
             }
         }
 
-        // lane column = row of M (rl), registers = columns nu
+        // lane column = row of M (rl), registers = columns nu.  A tile with
+        // every row and column inside C (all but the last, when M fills the
+        // row blocks) stores without per-lane tests, so its stores carry no
+        // exec branches.
+        if (P.M == M16 && (wk.u + 1) * COLS <= int64_t(P.N)) {
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-            const int cbase = int(wk.u * COLS) + (wave * FN + j) * 16;
+            for (int j = 0; j < FN; ++j) {
+                const int cbase = int(wk.u * COLS) + (wave * FN + j) * 16;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int col = cbase + RQ * kq + RR * r;
-                if (col < P.N) {
+                for (int r = 0; r < 4; ++r) {
+                    const int col = cbase + RQ * kq + RR * r;
                     TA* cp = C + grp_off1(uint32_t(col), P.gn) + int64_t(rl) * P.sCm;
-                    const int rmax = P.M - rl;
 #pragma unroll
-                    for (int i = 0; i < FM; ++i)
-                        if (i * 16 < rmax) cp[int64_t(i * 16) * P.sCm] = acc[i][j][r];
+                    for (int i = 0; i < FM; ++i) cp[int64_t(i * 16) * P.sCm] = acc[i][j][r];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const int cbase = int(wk.u * COLS) + (wave * FN + j) * 16;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int col = cbase + RQ * kq + RR * r;
+                    if (col < P.N) {
+                        TA* cp = C + grp_off1(uint32_t(col), P.gn) + int64_t(rl) * P.sCm;
+                        const int rmax = P.M - rl;
+#pragma unroll
+                        for (int i = 0; i < FM; ++i)
+                            if (i * 16 < rmax) cp[int64_t(i * 16) * P.sCm] = acc[i][j][r];
+                    }
                 }
             }
         }
