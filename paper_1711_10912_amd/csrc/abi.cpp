@@ -832,7 +832,7 @@ static int ttm_dispatch(const Ten& a, const Ten& bm, int mi, const Ten& c, int p
             const int64_t m16 = int64_t(fm) * 16, kp = int64_t(ks) * kstep;
             const int64_t lds =
                 wide ? m16 * (kp + 8) * 2 : kp * (m16 + (a.dtype == TLIB_F64 ? 4 : 16)) * esize(a.dtype);
-            if (ks > 0 && fm > 0 && Kr <= 64 && lds <= 65536 && fill_grp(T.gn, dn, ndn, 0, 1)) {
+            if (ks > 0 && fm > 0 && Kr <= 64 && lds <= 163840 && fill_grp(T.gn, dn, ndn, 0, 1)) {
                 T.X = bm.data;
                 T.Y = a.data;
                 T.C = c.data;
@@ -846,7 +846,7 @@ static int ttm_dispatch(const Ten& a, const Ten& bm, int mi, const Ten& c, int p
                 const int fn = fm >= 16 ? 1 : fm >= 4 ? 2 : 4;
                 const int64_t cols = 64 * fn;  // columns per workgroup tile
                 const int64_t tiles = (T.N + cols - 1) / cols;
-                const int per_cu = lds <= 20480 ? 4 : lds <= 40960 ? 3 : 2;
+                const int per_cu = lds <= 20480 ? 4 : lds <= 40960 ? 3 : lds <= 65536 ? 2 : 1;
                 const int grid = int(std::max<int64_t>(1, std::min<int64_t>(tiles, 256 * per_cu)));
                 plan_note("ttm stream dtype=%s M=%lld N=%d K=%lld dims=%d fm=%d cols=%lld ks=%d lds=%lld grid=%d "
                           "tiles=%lld",

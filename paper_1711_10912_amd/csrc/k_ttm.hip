@@ -437,6 +437,12 @@ static int stream_launch(const TtmParams& p, int grid, hipStream_t s) {
     constexpr int M16 = FM * 16;
     constexpr int PB = WIDE ? (KP + 8) : (M16 + (sizeof(TI) == 8 ? 4 : 16));
     const size_t lds = size_t(WIDE ? M16 * PB : KP * PB) * (WIDE ? 2 : sizeof(TI));
+    // gfx950 gives a workgroup up to 160 KB of LDS; above 64 KB the kernel
+    // has to ask for it
+    if (lds > 65536 &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&ttm_stream_kernel<TI, FM, FN, KS>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) != hipSuccess)
+        return TLIB_EHIP;
     hipLaunchKernelGGL((ttm_stream_kernel<TI, FM, FN, KS>), dim3(grid), dim3(256), lds, s, p);
     return hipGetLastError() == hipSuccess ? TLIB_OK : TLIB_EHIP;
 }

@@ -38,6 +38,8 @@ REGIMES = [
     ((70, 40, 9), [1, 2, 3], 2, 64, "mode=plain"),               # k = 40: no aligned depth
     ((24, 9, 11), [1, 2, 3], 1, 256, "ttm stream"),              # C contiguous along j
     ((5, 9, 11), [3, 2, 1], 3, 16, "ttm stream"),                # last-order, mode p
+    ((36, 9, 11), [1, 2, 3], 1, 256, "ttm stream"),              # B in LDS: 83 KB for FP64
+    ((60, 7, 9), [1, 2, 3], 1, 200, "ttm stream"),               # 133 KB for FP64, ragged m
     ((33, 29, 6), [1, 2, 3], 2, 300, "ttm gemm"),                # m > 256
     ((30, 200, 4), [1, 2, 3], 2, 64, "ttm gemm"),                # k = 200 > 64
 ]
