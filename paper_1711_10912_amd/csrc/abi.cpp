@@ -863,6 +863,9 @@ static int ttm_dispatch(const Ten& a, const Ten& bm, int mi, const Ten& c, int p
             const int lpc = 128 / esize(acc_dtype(a.dtype));  // C elements per 128-byte line
             int mode = TTM_ROWS_PLAIN;
             if (sclo == 1 && c.w[mi] == n_lo && n_lo <= 32) mode = n_lo <= 16 ? TTM_ROWS_BAND1 : TTM_ROWS_BAND;
+            else if (sclo == 1 && c.w[mi] == n_lo && n_lo > 128 && n_lo <= 176 &&
+                     ttm_rows_ks(a.dtype, TTM_ROWS_BANDW, int(std::min<int64_t>(Kr, 1 << 20))) > 0)
+                mode = TTM_ROWS_BANDW;
             else if (sclo == 1 && ttm_rows_ks(a.dtype, TTM_ROWS_ALIGNED, int(std::min<int64_t>(Kr, 1 << 20))) > 0)
                 mode = TTM_ROWS_ALIGNED;
             if (pick == TTM_PICK_ROWS_PLAIN) {
@@ -913,6 +916,7 @@ static int ttm_dispatch(const Ten& a, const Ten& bm, int mi, const Ten& c, int p
                           "rowgroups=%dx%d grid=%d",
                           dname(a.dtype),
                           mode == TTM_ROWS_BAND ? "band" : mode == TTM_ROWS_BAND1 ? "band1"
+                                                 : mode == TTM_ROWS_BANDW ? "bandw"
                                                  : mode == TTM_ROWS_ALIGNED ? "aligned" : "plain",
                           (long long)Mr, (long long)Kr, (long long)n_lo, (long long)(ncols / n_lo), (long long)tc, ks,
                           (long long)lds, nrg, mr, grid);

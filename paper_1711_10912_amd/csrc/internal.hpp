@@ -195,8 +195,9 @@ struct TtmParams {
 //                    line of C (needs sClo == 1; computes 128 bytes more)
 //   TTM_ROWS_BAND    whole runs, with rows j contiguous in C (sClo == 1,
 //                    sCm == n_lo): written as one linear range per row group
-//                    (two column blocks, n_lo <= 32; BAND1: one, n_lo <= 16)
-enum { TTM_ROWS_PLAIN = 0, TTM_ROWS_ALIGNED = 1, TTM_ROWS_BAND = 2, TTM_ROWS_BAND1 = 3 };
+//                    (two column blocks, n_lo <= 32; BAND1: one, n_lo <= 16;
+//                    BANDW: eleven, 128 < n_lo <= 176, FP32/FP64, k <= 16)
+enum { TTM_ROWS_PLAIN = 0, TTM_ROWS_ALIGNED = 1, TTM_ROWS_BAND = 2, TTM_ROWS_BAND1 = 3, TTM_ROWS_BANDW = 4 };
 struct TtmRowParams {
     const void* X;
     const void* Y;

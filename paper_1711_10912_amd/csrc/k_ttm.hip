@@ -265,7 +265,7 @@ __global__ __launch_bounds__(256) void ttm_rows_kernel(TtmRowParams P) {
     constexpr int SP = FN * 16 + 2;              // FP64 staging: row pitch
     constexpr int SPC = 20;                      // FP32 staging: column pitch (16-byte aligned)
     constexpr int STG = F64 ? SR * SP : FN * 16 * SPC;  // staged elements per wave
-    constexpr bool BAND = MODE == TTM_ROWS_BAND || MODE == TTM_ROWS_BAND1;
+    constexpr bool BAND = MODE == TTM_ROWS_BAND || MODE == TTM_ROWS_BAND1 || MODE == TTM_ROWS_BANDW;
     constexpr uint32_t OOB = 0x80000000u;       // buffer offset past every range: store dropped
     using RT = typename std::conditional<WIDE, uint16_t, TI>::type;
     static_assert(MODE != TTM_ROWS_ALIGNED || FN * 16 >= W + L, "aligned windows need W + L staged columns");
@@ -513,6 +513,7 @@ template <typename TI> constexpr int rows_fn(int mode) {
     return mode == TTM_ROWS_ALIGNED ? (64 + 128 / int(sizeof(typename AccOf<TI>::type))) / 16
            : mode == TTM_ROWS_PLAIN ? 4
            : mode == TTM_ROWS_BAND  ? 2
+           : mode == TTM_ROWS_BANDW ? 11
                                     : 1;
 }
 
@@ -541,10 +542,13 @@ int64_t ttm_rows_lds(int dtype, int mode, int m, int ks) {
 // k-step depths instantiated for the row kernel: aligned windows keep
 // FN * KS <= 36 fragments in registers.
 int ttm_rows_ks(int dtype, int mode, int k) {
-    if (dtype == TLIB_BF16 || dtype == TLIB_F16) return k <= 32 ? 1 : k <= 64 ? 2 : 0;
+    if (dtype == TLIB_BF16 || dtype == TLIB_F16) {
+        if (mode == TTM_ROWS_BANDW) return 0;
+        return k <= 32 ? 1 : k <= 64 ? 2 : 0;
+    }
     const int ks = (k + 3) / 4;
     static const int depths[] = {1, 2, 3, 4, 5, 6, 8, 10};
-    const int cap = mode == TTM_ROWS_ALIGNED ? 6 : 10;
+    const int cap = mode == TTM_ROWS_ALIGNED ? 6 : mode == TTM_ROWS_BANDW ? 4 : 10;
     for (int d : depths)
         if (ks <= d) return d <= cap ? d : 0;
     return 0;
@@ -563,9 +567,18 @@ static int rows_ks(const TtmRowParams& p, int ks, int grid, hipStream_t s) {
 #define TLIB_KS_CASE(K) \
     case K: return rows_launch<TI, MODE, K>(p, grid, s);
     if constexpr (sizeof(TI) == 2) {
+        if constexpr (MODE != TTM_ROWS_BANDW) {
+            switch (ks) {
+                TLIB_KS_CASE(1)
+                TLIB_KS_CASE(2)
+            }
+        }
+    } else if constexpr (MODE == TTM_ROWS_BANDW) {
         switch (ks) {
             TLIB_KS_CASE(1)
             TLIB_KS_CASE(2)
+            TLIB_KS_CASE(3)
+            TLIB_KS_CASE(4)
         }
     } else if constexpr (MODE == TTM_ROWS_ALIGNED) {
         switch (ks) {
@@ -599,6 +612,7 @@ static int rows_mode(const TtmRowParams& p, int mode, int ks, int grid, hipStrea
         case TTM_ROWS_ALIGNED: return rows_ks<TI, TTM_ROWS_ALIGNED>(p, ks, grid, s);
         case TTM_ROWS_BAND: return rows_ks<TI, TTM_ROWS_BAND>(p, ks, grid, s);
         case TTM_ROWS_BAND1: return rows_ks<TI, TTM_ROWS_BAND1>(p, ks, grid, s);
+        case TTM_ROWS_BANDW: return rows_ks<TI, TTM_ROWS_BANDW>(p, ks, grid, s);
     }
     return TLIB_EINVAL;
 }

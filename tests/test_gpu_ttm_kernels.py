@@ -33,8 +33,11 @@ REGIMES = [
     ((13, 13, 13, 13), [1, 2, 3, 4], 2, 7, "mode=band1"),        # m < 16
     ((20, 20, 20), [1, 2, 3], 2, 256, "mode=band "),             # n_lo = 20, two blocks
     ((29, 11, 9), [1, 2, 3], 2, 17, "mode=band "),               # n_lo = 29, ragged m
-    ((169, 13, 5), [1, 2, 3], 2, 100, "mode=aligned"),           # n_lo = 169: three windows
-    ((7, 5, 130), [3, 2, 1], 2, 33, "mode=aligned"),             # last-order: n_lo = 130
+    ((200, 13, 5), [1, 2, 3], 2, 100, "mode=aligned"),           # n_lo = 200: four windows
+    ((169, 13, 5), [1, 2, 3], 2, 100, "mode=bandw"),             # n_lo = 169, rows adjacent in C
+    ((130, 16, 7), [1, 2, 3], 2, 33, "mode=bandw"),              # k = 16: deepest band-wide depth
+    ((5, 13, 176), [3, 2, 1], 2, 40, "mode=bandw"),              # last-order, n_lo = 176
+    ((7, 5, 190), [3, 2, 1], 2, 33, "mode=aligned"),             # last-order: n_lo = 190
     ((70, 40, 9), [1, 2, 3], 2, 64, "mode=plain"),               # k = 40: no aligned depth
     ((24, 9, 11), [1, 2, 3], 1, 256, "ttm stream"),              # C contiguous along j
     ((5, 9, 11), [3, 2, 1], 3, 16, "ttm stream"),                # last-order, mode p
