@@ -142,10 +142,13 @@ struct tlib_server {
     std::thread th;
     bool stop = false;
     std::atomic<int> busy_slots{0};
+    bool dev_err = false;  // the server thread could not select its device: every job fails
 
+    // device-clock time of a recorded event on the host timeline; a failed
+    // query (an event that was never recorded) reads as the reference time
     double ev_time(hipEvent_t ev) {
         float ms = 0.f;
-        hipEventElapsedTime(&ms, ref, ev);
+        if (hipEventElapsedTime(&ms, ref, ev) != hipSuccess) ms = 0.f;
         return t_ref + double(ms) * 1e-3;
     }
 
@@ -176,6 +179,10 @@ struct tlib_server {
 
     void launch_single(Slot& s, Job* j) {
         place_output(j);
+        if (dev_err) {
+            j->err = TLIB_EHIP;
+            return;
+        }
         void* st = (void*)s.stream;
         if (j->op == 0) j->err = tlib_ttv(&j->a.t, &j->b.t, j->mode, &j->c.t, st);
         else if (j->op == 1) j->err = tlib_ttm(&j->a.t, &j->b.t, j->mode, &j->c.t, st);
@@ -196,10 +203,16 @@ struct tlib_server {
             for (Job* j : jobs) launch_single(s, j);
             return;
         }
-        hipMemcpyAsync(s.tab_dev, s.tab_host, tlib_batch_table_bytes(int32_t(req.size())), hipMemcpyHostToDevice,
-                       s.stream);
-        if (s.graph) hipGraphLaunch(s.graph, s.stream);
-        else tlib_batch_run(s.tab_dev, grid, (void*)s.stream);
+        int err = dev_err ? TLIB_EHIP : TLIB_OK;
+        if (!err && hipMemcpyAsync(s.tab_dev, s.tab_host, tlib_batch_table_bytes(int32_t(req.size())),
+                                   hipMemcpyHostToDevice, s.stream) != hipSuccess)
+            err = TLIB_EHIP;
+        if (!err) {
+            if (s.graph) err = hipGraphLaunch(s.graph, s.stream) == hipSuccess ? TLIB_OK : TLIB_EHIP;
+            else err = tlib_batch_run(s.tab_dev, grid, (void*)s.stream);
+        }
+        if (err)
+            for (Job* j : jobs) j->err = err;
     }
 
     bool admit() {
@@ -229,14 +242,18 @@ struct tlib_server {
         } else {
             launch_single(*slot, head);
         }
-        hipEventRecord(slot->done, slot->stream);
+        // an event that cannot be recorded reads as complete: the slot's
+        // jobs are then reported failed instead of waiting forever
+        if (hipEventRecord(slot->done, slot->stream) != hipSuccess)
+            for (Job* j : jobs)
+                if (!j->err) j->err = TLIB_EHIP;
         slot->jobs = jobs;
         ++busy_slots;
         return true;
     }
 
     void loop() {
-        hipSetDevice(device);
+        if (hipSetDevice(device) != hipSuccess) dev_err = true;
         std::unique_lock<std::mutex> lk(mu);
         while (!stop) {
             retire();
