@@ -516,7 +516,7 @@ static int tuned(const std::string& key, const int* cands, int nc, hipStream_t s
             if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
                 return fail(TLIB_EHIP, "autotune: event wait failed");
             float ms = 0.f;
-            hipEventElapsedTime(&ms, e0, e1);
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return fail(TLIB_EHIP, "autotune: event time failed");
             if (round == 0 || ms < tmin[i]) tmin[i] = ms;
         }
     int bp = PICK_NA;

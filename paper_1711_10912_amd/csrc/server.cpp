@@ -311,14 +311,17 @@ tlib_server* tlib_server_create(int32_t device, size_t output_budget, int32_t sl
             if (hipStreamEndCapture(s.stream, &g) == hipSuccess && rc == TLIB_OK && g) {
                 if (hipGraphInstantiate(&s.graph, g, nullptr, nullptr, 0) != hipSuccess) s.graph = nullptr;
             }
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
         }
         (void)hipGetLastError();
     }
-    hipEventCreate(&S->ref);
-    hipDeviceSynchronize();
-    hipEventRecord(S->ref, S->slots[0].stream);
-    hipEventSynchronize(S->ref);
+    // reference event: device time zero on the host clock
+    if (hipEventCreate(&S->ref) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+        hipEventRecord(S->ref, S->slots[0].stream) != hipSuccess || hipEventSynchronize(S->ref) != hipSuccess) {
+        (void)hipGetLastError();
+        tlib_server_destroy(S);
+        return nullptr;
+    }
     S->t_ref = now_s();
     S->th = std::thread([S] { S->loop(); });
     return S;
@@ -445,16 +448,18 @@ void tlib_server_destroy(tlib_server* S) {
         S->cv.notify_one();
         S->th.join();
     }
+    // best-effort release: a failure here leaves nothing to recover
     for (auto& s : S->slots) {
-        if (s.stream) hipStreamSynchronize(s.stream);
-        if (s.graph) hipGraphExecDestroy(s.graph);
-        if (s.done) hipEventDestroy(s.done);
-        if (s.tab_host) hipHostFree(s.tab_host);
-        if (s.tab_dev) hipFree(s.tab_dev);
-        if (s.stream) hipStreamDestroy(s.stream);
+        if (s.stream) (void)hipStreamSynchronize(s.stream);
+        if (s.graph) (void)hipGraphExecDestroy(s.graph);
+        if (s.done) (void)hipEventDestroy(s.done);
+        if (s.tab_host) (void)hipHostFree(s.tab_host);
+        if (s.tab_dev) (void)hipFree(s.tab_dev);
+        if (s.stream) (void)hipStreamDestroy(s.stream);
     }
-    if (S->ref) hipEventDestroy(S->ref);
-    if (S->arena_ptr) hipFree(S->arena_ptr);
+    if (S->ref) (void)hipEventDestroy(S->ref);
+    if (S->arena_ptr) (void)hipFree(S->arena_ptr);
+    (void)hipGetLastError();
     for (Job* j : S->completed) delete j;
     for (Job* j : S->pending) delete j;
     delete S;
