@@ -605,22 +605,24 @@ static int run_gemm(int dtype, const void* X, const void* Y, void* C, Dim* dm, i
             }
         }
         {
-            // 16-bit operands whose K has a first dim of unit stride (extent a
-            // multiple of 8) load 16-byte groups of 8 consecutive k; every
-            // other stride and the base keep the groups 16-byte aligned.
+            // Operands whose K has a first dim of unit stride load groups of
+            // consecutive k (16-bit X and Y: 8 k; FP32/FP64 X: 2 k), where
+            // that dim's extent is a multiple of the group and every other
+            // stride and the base keep the groups aligned.
             P.kvec = 0;
-            if ((dtype == TLIB_BF16 || dtype == TLIB_F16) && ndk >= 1 && dk[0].n % 8 == 0) {
-                auto groups_ok = [&](int o, const void* base, const Dim* d, int nd) {
-                    if (dk[0].s[o] != 1 || (uintptr_t(base) % 16) != 0) return false;
-                    for (int i = 1; i < ndk; ++i)
-                        if (dk[i].s[o] % 8 != 0) return false;
-                    for (int i = 0; i < nd; ++i)
-                        if (d[i].s[0] % 8 != 0) return false;
-                    return true;
-                };
-                if (groups_ok(0, X, dm, ndm)) P.kvec |= 1;
-                if (groups_ok(1, Y, dn, ndn)) P.kvec |= 2;
-            }
+            const bool wide = dtype == TLIB_BF16 || dtype == TLIB_F16;
+            const int gv = wide ? 8 : 2;  // k per group: 16 bytes (16-bit, FP64) or 8 bytes (FP32)
+            const int gb = gv * esize(dtype);
+            auto groups_ok = [&](int o, const void* base, const Dim* d, int nd) {
+                if (ndk < 1 || dk[0].n % gv != 0 || dk[0].s[o] != 1 || (uintptr_t(base) % gb) != 0) return false;
+                for (int i = 1; i < ndk; ++i)
+                    if (dk[i].s[o] % gv != 0) return false;
+                for (int i = 0; i < nd; ++i)
+                    if (d[i].s[0] % gv != 0) return false;
+                return true;
+            };
+            if (groups_ok(0, X, dm, ndm)) P.kvec |= 1;
+            if (wide && groups_ok(1, Y, dn, ndn)) P.kvec |= 2;
         }
         // FP64 accumulators are twice as wide: keep a wave's tile at 64x32 so
         // that two waves fit per SIMD.

@@ -26,6 +26,7 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
 typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u2_t __attribute__((ext_vector_type(2)));
 
 // Source of the loads that fall outside X or Y: selecting the address rather
 // than the loaded value keeps the loads unconditional, without an exec branch
@@ -111,15 +112,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
     constexpr int EX = BM * BK / 256;  // X elements per thread per K slice
     constexpr int EY = BN * BK / 256;
     static_assert(EX >= 1 && EY >= 1, "tile too small");
-    // FP32/FP64: YW > 0 = Y as vectors along N.  16-bit: YW bit 0 / bit 1 =
-    // X / Y loaded as 16-byte groups of 8 consecutive k (see fetch).
-    constexpr bool YV = !WIDE && YW > 0;
-    constexpr bool XKV = WIDE && (YW & 1) != 0;
+    // FP32/FP64: YW & 15 > 0 = Y as vectors of that many elements along N;
+    // YW & 16 = X loaded as groups of 2 consecutive k.  16-bit: YW bit 0 /
+    // bit 1 = X / Y loaded as 16-byte groups of 8 consecutive k (see fetch).
+    constexpr bool YV = !WIDE && (YW & 15) > 0;
+    constexpr bool XKV = WIDE ? (YW & 1) != 0 : (YW & 16) != 0;
     constexpr bool YKV = WIDE && (YW & 2) != 0;
-    constexpr int KG = BK / 8;                     // 8-element k groups per slice
-    constexpr int NXV = BM * KG, NYV = BN * KG;    // k groups per X / Y slice
+    constexpr int GVX = WIDE ? 8 : 2;              // k per X group
+    constexpr int KGX = BK / GVX;                  // X groups per slice row
+    constexpr int KG = BK / 8;                     // 8-element Y k groups per slice (16-bit)
+    constexpr int NXV = BM * KGX, NYV = BN * KG;   // k groups per X / Y slice
     constexpr int EXV = (NXV + 255) / 256, EYK = (NYV + 255) / 256;
-    constexpr int VY = YV ? YW : 1;
+    using xg_t = typename std::conditional<(WIDE || sizeof(TI) == 8), u4_t, u2_t>::type;
+    constexpr int VY = YV ? (YW & 15) : 1;
     constexpr int CG = BN / VY;                   // column groups of a Y slice
     constexpr int RS = YV ? 256 / CG : 1;         // rows of the slice per pass
     constexpr int EYV = YV ? BK / RS : 1;         // vectors per thread per slice
@@ -199,7 +204,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
 
     RT xr[XKV ? 1 : EX], yr[(YV || YKV) ? 1 : EY];
     yv_t yvr[EYV];
-    u4_t xg[XKV ? EXV : 1], yg[YKV ? EYK : 1];
+    xg_t xg[XKV ? EXV : 1];
+    u4_t yg[YKV ? EYK : 1];
     // YV: this thread's column group and first row, the group's offset and
     // whether every thread of the wave has VY consecutive, aligned columns
     const int ycg = tid % CG, yrow = tid / CG;
@@ -207,19 +213,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
     bool wvec = false;
     int k0n = 0;  // first k of the slice being fetched
     const TI* zsrc = reinterpret_cast<const TI*>(g_gemm_zero);
-    // 16-bit k groups: slot e = tid + 256 j is group e % KG of row / column
-    // e / KG.  The host enables them only where K's first dim has unit stride
-    // in the operand and a multiple of 8 extent and every other stride keeps
-    // the groups 16-byte aligned, so the group starting at a valid k is
-    // wholly inside the slice's K range and contiguous in memory.
+    // k groups: slot e = tid + 256 j is group e % KGX (X) or e % KG (16-bit
+    // Y) of row / column e / KGX (e / KG).  The host enables them only where
+    // K's first dim has unit stride in the operand and a multiple of the
+    // group as extent and every other stride keeps the groups aligned, so
+    // the group starting at a valid k is wholly inside the slice's K range
+    // and contiguous in memory.
     auto fetch = [&](int slot) {
         if constexpr (XKV) {
 #pragma unroll
             for (int j = 0; j < EXV; ++j) {
                 const int e = tid + j * 256;
-                const int mm = min(e / KG, BM - 1), kv = e % KG;
-                const int64_t a = e < NXV ? xrow[mm] : -1, b = kx[slot][kv * 8];
-                xg[j] = *reinterpret_cast<const u4_t*>((a >= 0 && b >= 0) ? X + (a + b) : zsrc);
+                const int mm = min(e / KGX, BM - 1), kv = e % KGX;
+                const int64_t a = e < NXV ? xrow[mm] : -1, b = kx[slot][kv * GVX];
+                xg[j] = *reinterpret_cast<const xg_t*>((a >= 0 && b >= 0) ? X + (a + b) : zsrc);
             }
         } else {
 #pragma unroll
@@ -277,7 +284,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
 #pragma unroll
             for (int j = 0; j < EXV; ++j) {
                 const int e = tid + j * 256;
-                if (e < NXV) *reinterpret_cast<u4_t*>(&Xs[(e / KG) * PX + (e % KG) * 8]) = xg[j];
+                if constexpr (WIDE) {
+                    if (e < NXV) *reinterpret_cast<u4_t*>(&Xs[(e / KGX) * PX + (e % KGX) * GVX]) = xg[j];
+                } else if (e < NXV) {
+                    // k-major tile: the group's two k go to two rows
+                    struct Pair {
+                        TI v[2];
+                    };
+                    const Pair pv = __builtin_bit_cast(Pair, xg[j]);
+                    const int mm = e / KGX, k2 = (e % KGX) * 2;
+                    Xs[k2 * PX + mm] = pv.v[0];
+                    Xs[(k2 + 1) * PX + mm] = pv.v[1];
+                }
             }
         } else {
 #pragma unroll
@@ -471,13 +489,27 @@ static int gemm_launch(const GemmParams& p, hipStream_t s) {
     using TA = typename AccOf<TI>::type;
     const unsigned tiles = unsigned(p.tiles_m) * unsigned(p.tiles_n);
     const dim3 grid(tiles, unsigned(p.ksplit));
+#define TLIB_GEMM(VM) hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, VM>), grid, dim3(256), 0, s, p)
+    const bool xg = (p.kvec & 1) != 0;
     if constexpr (sizeof(TI) == 8) {
-        if (p.y_vec == 2) hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 2>), grid, dim3(256), 0, s, p);
-        else hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 0>), grid, dim3(256), 0, s, p);
+        if (p.y_vec == 2) {
+            if (xg) TLIB_GEMM(18);
+            else TLIB_GEMM(2);
+        } else {
+            if (xg) TLIB_GEMM(16);
+            else TLIB_GEMM(0);
+        }
     } else if constexpr (sizeof(TI) == 4) {
-        if (p.y_vec == 4) hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 4>), grid, dim3(256), 0, s, p);
-        else if (p.y_vec == 2) hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 2>), grid, dim3(256), 0, s, p);
-        else hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 0>), grid, dim3(256), 0, s, p);
+        if (p.y_vec == 4) {
+            if (xg) TLIB_GEMM(20);
+            else TLIB_GEMM(4);
+        } else if (p.y_vec == 2) {
+            if (xg) TLIB_GEMM(18);
+            else TLIB_GEMM(2);
+        } else {
+            if (xg) TLIB_GEMM(16);
+            else TLIB_GEMM(0);
+        }
     } else {
         switch (p.kvec) {
             case 1: hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 1>), grid, dim3(256), 0, s, p); break;
@@ -486,6 +518,7 @@ static int gemm_launch(const GemmParams& p, hipStream_t s) {
             default: hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 0>), grid, dim3(256), 0, s, p);
         }
     }
+#undef TLIB_GEMM
     if (hipGetLastError() != hipSuccess) return TLIB_EHIP;
     if (p.ksplit > 1) {
         const int64_t MN = int64_t(p.M) * p.N;
