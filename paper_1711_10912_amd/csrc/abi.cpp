@@ -606,7 +606,7 @@ static int run_gemm(int dtype, const void* X, const void* Y, void* C, Dim* dm, i
         }
         {
             // Operands whose K has a first dim of unit stride load groups of
-            // consecutive k (16-bit X and Y: 8 k; FP32/FP64 X: 2 k), where
+            // consecutive k (16-bit: 8 k; FP32/FP64: 2 k), where
             // that dim's extent is a multiple of the group and every other
             // stride and the base keep the groups aligned.
             P.kvec = 0;
@@ -622,7 +622,7 @@ static int run_gemm(int dtype, const void* X, const void* Y, void* C, Dim* dm, i
                 return true;
             };
             if (groups_ok(0, X, dm, ndm)) P.kvec |= 1;
-            if (wide && groups_ok(1, Y, dn, ndn)) P.kvec |= 2;
+            if (P.y_vec == 0 && groups_ok(1, Y, dn, ndn)) P.kvec |= 2;
         }
         // FP64 accumulators are twice as wide: keep a wave's tile at 64x32 so
         // that two waves fit per SIMD.

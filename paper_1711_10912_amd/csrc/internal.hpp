@@ -114,7 +114,7 @@ struct GemmParams {
     void* part;              // split-K partials [ksplit][M][N] (accumulator type)
     int32_t y_vec;           // > 0: Y loaded as vectors of y_vec elements along N (K one dim, stride syk)
     int64_t syk;
-    int32_t kvec;            // bit 0: X loaded as groups of consecutive k (8 for 16-bit, 2 for FP32/FP64); bit 1: Y (16-bit only)
+    int32_t kvec;            // bit 0 / bit 1: X / Y loaded as groups of consecutive k (8 for 16-bit, 2 for FP32/FP64)
 };
 
 // Multi-mode TTV (one pass over A).  A group of modes in storage order,

@@ -113,14 +113,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
     constexpr int EY = BN * BK / 256;
     static_assert(EX >= 1 && EY >= 1, "tile too small");
     // FP32/FP64: YW & 15 > 0 = Y as vectors of that many elements along N;
-    // YW & 16 = X loaded as groups of 2 consecutive k.  16-bit: YW bit 0 /
-    // bit 1 = X / Y loaded as 16-byte groups of 8 consecutive k (see fetch).
+    // YW & 16 / YW & 32 = X / Y loaded as groups of 2 consecutive k.  16-bit:
+    // YW bit 0 / bit 1 = X / Y loaded as 16-byte groups of 8 consecutive k
+    // (see fetch).
     constexpr bool YV = !WIDE && (YW & 15) > 0;
     constexpr bool XKV = WIDE ? (YW & 1) != 0 : (YW & 16) != 0;
-    constexpr bool YKV = WIDE && (YW & 2) != 0;
-    constexpr int GVX = WIDE ? 8 : 2;              // k per X group
-    constexpr int KGX = BK / GVX;                  // X groups per slice row
-    constexpr int KG = BK / 8;                     // 8-element Y k groups per slice (16-bit)
+    constexpr bool YKV = WIDE ? (YW & 2) != 0 : (YW & 32) != 0;
+    constexpr int GVX = WIDE ? 8 : 2;              // k per X / Y group
+    constexpr int KGX = BK / GVX;                  // groups per slice row
+    constexpr int KG = KGX;
     constexpr int NXV = BM * KGX, NYV = BN * KG;   // k groups per X / Y slice
     constexpr int EXV = (NXV + 255) / 256, EYK = (NYV + 255) / 256;
     using xg_t = typename std::conditional<(WIDE || sizeof(TI) == 8), u4_t, u2_t>::type;
@@ -205,7 +206,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
     RT xr[XKV ? 1 : EX], yr[(YV || YKV) ? 1 : EY];
     yv_t yvr[EYV];
     xg_t xg[XKV ? EXV : 1];
-    u4_t yg[YKV ? EYK : 1];
+    xg_t yg[YKV ? EYK : 1];
     // YV: this thread's column group and first row, the group's offset and
     // whether every thread of the wave has VY consecutive, aligned columns
     const int ycg = tid % CG, yrow = tid / CG;
@@ -242,8 +243,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
             for (int j = 0; j < EYK; ++j) {
                 const int e = tid + j * 256;
                 const int nn = min(e / KG, BN - 1), kv = e % KG;
-                const int64_t a = e < NYV ? ycol[nn] : -1, b = ky[slot][kv * 8];
-                yg[j] = *reinterpret_cast<const u4_t*>((a >= 0 && b >= 0) ? Y + (a + b) : zsrc);
+                const int64_t a = e < NYV ? ycol[nn] : -1, b = ky[slot][kv * GVX];
+                yg[j] = *reinterpret_cast<const xg_t*>((a >= 0 && b >= 0) ? Y + (a + b) : zsrc);
             }
         } else if constexpr (YV) {
             // the choice is per wave (wvec is uniform), so only one of the two
@@ -310,7 +311,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
 #pragma unroll
             for (int j = 0; j < EYK; ++j) {
                 const int e = tid + j * 256;
-                if (e < NYV) *reinterpret_cast<u4_t*>(&Ys[(e / KG) * PY + (e % KG) * 8]) = yg[j];
+                if constexpr (WIDE) {
+                    if (e < NYV) *reinterpret_cast<u4_t*>(&Ys[(e / KG) * PY + (e % KG) * GVX]) = yg[j];
+                } else if (e < NYV) {
+                    struct Pair {
+                        TI v[2];
+                    };
+                    const Pair pv = __builtin_bit_cast(Pair, yg[j]);
+                    const int nn = e / KG, k2 = (e % KG) * 2;
+                    Ys[k2 * PY + nn] = pv.v[0];
+                    Ys[(k2 + 1) * PY + nn] = pv.v[1];
+                }
             }
         } else if constexpr (YV) {
 #pragma unroll
@@ -492,7 +503,10 @@ static int gemm_launch(const GemmParams& p, hipStream_t s) {
 #define TLIB_GEMM(VM) hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, VM>), grid, dim3(256), 0, s, p)
     const bool xg = (p.kvec & 1) != 0;
     if constexpr (sizeof(TI) == 8) {
-        if (p.y_vec == 2) {
+        if (p.kvec & 2) {  // Y in k groups (then no vectors along N)
+            if (xg) TLIB_GEMM(48);
+            else TLIB_GEMM(32);
+        } else if (p.y_vec == 2) {
             if (xg) TLIB_GEMM(18);
             else TLIB_GEMM(2);
         } else {
@@ -500,7 +514,10 @@ static int gemm_launch(const GemmParams& p, hipStream_t s) {
             else TLIB_GEMM(0);
         }
     } else if constexpr (sizeof(TI) == 4) {
-        if (p.y_vec == 4) {
+        if (p.kvec & 2) {
+            if (xg) TLIB_GEMM(48);
+            else TLIB_GEMM(32);
+        } else if (p.y_vec == 4) {
             if (xg) TLIB_GEMM(20);
             else TLIB_GEMM(4);
         } else if (p.y_vec == 2) {

@@ -1,6 +1,7 @@
-"""GPU parity of the GEMM path with 16-bit operands loaded as 16-byte groups
-of eight consecutive k (TTT, Sec. 5.2 Eq. ttt, and TTM, Eq. ttm), against the
-oracle on the same rounded inputs (FP32 accumulation: 1e-5 normwise).  The
+"""GPU parity of the GEMM path with operands loaded as groups of consecutive
+k (16-bit: 16-byte groups of eight; FP32/FP64: groups of two) for TTT (Sec.
+5.2 Eq. ttt) and TTM (Eq. ttm), against the oracle on the same rounded inputs
+(16-bit with FP32 accumulation and FP32: 1e-5 normwise; FP64: 1e-12).  The
 cases put K's unit-stride dim in X, in Y, in both and in neither, with ragged
 M and N, several tile shapes and split-K; the full-size TTT runs with the
 shipped kernel table, i.e. the tiles the benchmark times."""
@@ -12,7 +13,7 @@ import pytest
 
 import oracle
 import synth
-from _util import TOL_KERNEL16, assert_close, round_to, to_gpu, to_np
+from _util import TOL, TOL_KERNEL16, assert_close, round_to, to_gpu, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -37,7 +38,7 @@ A_LAYOUTS = [[1, 2, 3], [3, 2, 1], [2, 3, 1]]
 B_LAYOUTS = [[1, 2, 3], [3, 1, 2], [2, 1, 3]]
 
 
-@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+@pytest.mark.parametrize("dtype", ["bf16", "f16", "f32", "f64"])
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
 def test_ttt_k_groups(T, dtype, shape):
     import torch
@@ -51,14 +52,17 @@ def test_ttt_k_groups(T, dtype, shape):
     for la in A_LAYOUTS:
         for lb in B_LAYOUTS:
             Ad, Bd = to_gpu(X, la, dtype), to_gpu(Y, lb, dtype)
-            C = T.empty((M1, N1), None, torch.float32, "cuda")
+            C = T.empty((M1, N1), None, torch.float64 if dtype == "f64" else torch.float32, "cuda")
             plan = T.plan(T.ttt, Ad, Bd, 2, (1, 2, 3), (3, 1, 2), out=C)
             seen.add(_kvec(plan))
             C.fill_(float("nan"))
             T.ttt(Ad, Bd, 2, (1, 2, 3), (3, 1, 2), out=C)
-            assert_close(to_np(C), ref, TOL_KERNEL16, "%s %s A%s B%s" % (plan, dtype, la, lb))
-    if K2 % 8 == 0:
+            tol = TOL[dtype] if dtype in ("f32", "f64") else TOL_KERNEL16
+            assert_close(to_np(C), ref, tol, "%s %s A%s B%s" % (plan, dtype, la, lb))
+    if dtype in ("bf16", "f16") and K2 % 8 == 0:
         assert {1, 2, 3} <= seen, seen
+    if dtype in ("f32", "f64"):
+        assert seen - {0}, seen
 
 
 @pytest.mark.parametrize("dtype", ["bf16", "f16"])
