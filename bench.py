@@ -696,7 +696,7 @@ def main():
     kern = {}
     for c in cases:
         k = kern.setdefault(c.kernel, {"launches": 0, "ms": 0.0, "bytes": 0.0, "flops": 0.0, "t_hbm": 0.0,
-                                       "t_mfma": 0.0, "dtype": c.dtype, "family": c.family})
+                                       "t_mfma": 0.0, "ideal": 0.0, "dtype": c.dtype, "family": c.family})
         avg = sum(c.ms) / len(c.ms)
         k["launches"] += 1
         k["ms"] += avg
@@ -704,6 +704,7 @@ def main():
         k["flops"] += c.flops
         k["t_hbm"] += c.bytes / PEAK_HBM
         k["t_mfma"] += c.flops / PEAK_FLOPS[c.dtype]
+        k["ideal"] += c.ideal_s()
     dom_name = max(kern, key=lambda n: kern[n]["ms"])
     dk = kern[dom_name]
     if dk["t_hbm"] >= dk["t_mfma"]:
@@ -723,6 +724,10 @@ def main():
     roof["kernel"] = dom_name
     roof["launches_per_step"] = dk["launches"]
     roof["avg_launch_us"] = round(dk["ms"] * 1e3 / dk["launches"], 2)
+    # each launch priced at its own bound (HBM or MFMA, whichever takes
+    # longer): a kernel whose launches differ in bound reaches more of that
+    # roofline than `frac`, which prices them all at one bound
+    roof["frac_per_launch_bound"] = round(dk["ideal"] / (dk["ms"] * 1e-3), 4)
 
     fam = {}
     for c in cases:
@@ -739,7 +744,7 @@ def main():
     kernels = {n: {"launches": k["launches"], "ms": round(k["ms"], 3),
                    "GB/s": round(k["bytes"] / (k["ms"] * 1e-3) / 1e9, 1),
                    "TFLOP/s": round(k["flops"] / (k["ms"] * 1e-3) / 1e12, 3),
-                   "roofline_frac": round(max(k["t_hbm"], k["t_mfma"]) / (k["ms"] * 1e-3), 4)}
+                   "roofline_frac": round(k["ideal"] / (k["ms"] * 1e-3), 4)}
                for n, k in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])}
 
     if args.cases_out:
