@@ -334,7 +334,14 @@ static int run_ttv(const Ten& a, const Ten& b, int mi, const Ten& c, hipStream_t
         P.sA_hi = P.sC_hi = 0;
     }
 
-    if ((fast && P.n_lo >= 32) || colview) {
+    // dense operand: its (lo,k) slabs are contiguous.  For n_lo of 32..63
+    // the slab kernel (b staged in LDS beside the slabs) beats lanes along lo
+    // when whole slabs fit its 32 KB and there are enough of them to fill the
+    // chip; otherwise the col kernel (with its k splits) keeps those shapes.
+    const bool slabs_dense = fast && (P.n_lo == 1 || P.sA_lo == 1) && (P.n_k == 1 || P.sA_k == P.n_lo) &&
+                             (P.n_hi == 1 || P.sA_hi == P.n_lo * P.n_k);
+    const bool mid_slabs = slabs_dense && P.n_lo * P.n_k * esize(a.dtype) <= 32768 && P.n_hi >= 2048;
+    if ((fast && (P.n_lo >= 64 || (P.n_lo >= 32 && !mid_slabs))) || colview) {
         const int maxvec = 16 / es;
         auto vec_ok = [&](int v) {
             if (v == 1) return true;
@@ -387,8 +394,7 @@ static int run_ttv(const Ten& a, const Ten& b, int mi, const Ten& c, hipStream_t
     // contiguous fiber, which the fiber kernel streams without staging
     // (below); shorter fibers fill its lane groups poorly and stay on slabs
     const bool row_fibers = fast && P.n_lo == 1 && P.sA_k == 1 && P.n_k >= 32;
-    const bool slab_ok = fast && !row_fibers && (P.n_lo == 1 || P.sA_lo == 1) && (P.n_k == 1 || P.sA_k == P.n_lo) &&
-                         (P.n_hi == 1 || P.sA_hi == P.n_lo * P.n_k);
+    const bool slab_ok = slabs_dense && !row_fibers;
     if (slab_ok) {
         const int64_t cap = 32768 / es;
         const int64_t slab = P.n_lo * P.n_k;

@@ -3,16 +3,17 @@
 // where lo gathers the output modes whose A-stride is below the contracted
 // mode's and hi the ones above.  TTV streams A once and is HBM-bound, so the
 // kernels are organised around coalesced reads of A:
-//   col   (n_lo >= 32): lanes run along lo (unit stride), the four waves of a
+//   col   (n_lo >= 64, or >= 32 without contiguous slabs): lanes run along lo (unit stride), the four waves of a
 //         workgroup take interleaved k and are summed through LDS in a fixed
 //         order; optional grid split over k with a second summing pass.  The
 //         hi index is decoded over up to four dims, so views whose outer dims
 //         do not merge (ranges, steps) stay on this kernel.
 //         With a short k (and no grid split) each wave owns a whole
 //         (lo tile, hi) unit instead and keeps all of its rows in flight.
-//   slab  (n_lo < 32 and the (lo,k) slabs contiguous): a workgroup copies whole
-//         contiguous slabs into LDS with coalesced loads, then groups of G lanes
-//         reduce each output's k-fiber out of LDS with a shuffle tree.
+//   slab  (n_lo < 64 and the (lo,k) slabs contiguous): a workgroup copies whole
+//         contiguous slabs (and b, when short) into LDS with coalesced loads,
+//         then groups of G lanes reduce each output's k-fiber out of LDS with a
+//         shuffle tree.
 //   fiber (n_lo < 32, slabs not contiguous: views; and n_lo = 1 with k of
 //         unit stride and n_k >= 32, where every output is one contiguous
 //         fiber): G lanes per output stream its k-fiber (coalesced when k has
@@ -168,8 +169,10 @@ __global__ __launch_bounds__(256) void ttv_ksum_kernel(TtvParams P, int ksplit, 
 }
 
 // LDS holds `slabs` consecutive (lo,k)-slabs, restricted to k rows [k0, k0+kc).
+// bl: whole slabs (kc >= n_k) and b staged in LDS behind them (16-byte
+// aligned), so that the dot loops read both operands from LDS.
 template <typename TI>
-__global__ __launch_bounds__(256) void ttv_slab_kernel(TtvParams P, int slabs, int kc) {
+__global__ __launch_bounds__(256) void ttv_slab_kernel(TtvParams P, int slabs, int kc, int bl) {
     using TA = typename AccOf<TI>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     TI* L = reinterpret_cast<TI*>(smem_raw);
@@ -218,6 +221,9 @@ __global__ __launch_bounds__(256) void ttv_slab_kernel(TtvParams P, int slabs, i
             L[i + 768] = v3;
         }
         for (; i < total; i += 256) L[i] = src[i];
+        TI* Lb = reinterpret_cast<TI*>(smem_raw + ((size_t(slabs) * size_t(slab) * sizeof(TI) + 15) & ~size_t(15)));
+        if (bl)
+            for (int e = tid; e < int(n_k); e += 256) Lb[e] = b[int64_t(e) * P.sb];
         __syncthreads();
         for (int base = 0; base < O * G; base += 256) {
             const int t = base + tid;
@@ -226,7 +232,13 @@ __global__ __launch_bounds__(256) void ttv_slab_kernel(TtvParams P, int slabs, i
             if (o < O) {
                 const int hl = o / n_lo, lo = o - hl * n_lo;
                 const TI* Ls = L + int64_t(hl) * slab + lo;
-                for (int64_t k = g; k < n_k; k += G) acc += to_acc(Ls[k * n_lo]) * to_acc(b[k * P.sb]);
+                if (bl) {
+                    const int nk = int(n_k);
+#pragma unroll 4
+                    for (int k = g; k < nk; k += G) acc += to_acc(Ls[k * n_lo]) * to_acc(Lb[k]);
+                } else {
+                    for (int64_t k = g; k < n_k; k += G) acc += to_acc(Ls[k * n_lo]) * to_acc(b[k * P.sb]);
+                }
             }
             if (G > 1) acc = warp_sum(acc, G);
             if (o < O && g == 0) {
@@ -235,7 +247,7 @@ __global__ __launch_bounds__(256) void ttv_slab_kernel(TtvParams P, int slabs, i
             }
         }
     } else {
-        // one slab (nS == 1) taken kc rows at a time; O = n_lo < 32 so O*G <= 256
+        // one slab (nS == 1) taken kc rows at a time; O = n_lo < 64 so O*G <= 256
         const int o = tid / G, g = tid % G;
         TA acc = TA(0);
         const TI* src0 = A + h0 * slab;
@@ -410,8 +422,11 @@ template <typename TI>
 static int slab_launch(const TtvParams& p, int slabs, int kc, hipStream_t s) {
     const int64_t blocks = (p.n_hi + slabs - 1) / slabs;
     const int64_t rows = kc >= p.n_k ? p.n_k : kc;
-    const size_t lds = size_t(slabs) * size_t(rows) * size_t(p.n_lo) * sizeof(TI);
-    hipLaunchKernelGGL((ttv_slab_kernel<TI>), dim3(unsigned(blocks)), dim3(256), lds, s, p, slabs, kc);
+    size_t lds = size_t(slabs) * size_t(rows) * size_t(p.n_lo) * sizeof(TI);
+    // b joins the slabs in LDS when they are whole and it is small
+    const int bl = kc >= p.n_k && p.n_k * int64_t(sizeof(TI)) <= 4096 ? 1 : 0;
+    if (bl) lds = ((lds + 15) & ~size_t(15)) + size_t(p.n_k) * sizeof(TI);
+    hipLaunchKernelGGL((ttv_slab_kernel<TI>), dim3(unsigned(blocks)), dim3(256), lds, s, p, slabs, kc, bl);
     return hipGetLastError() == hipSuccess ? TLIB_OK : TLIB_EHIP;
 }
 

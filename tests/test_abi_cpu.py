@@ -85,6 +85,21 @@ def test_ttv_regimes():
         b20 = _d((20,), ptr=FAKE * 2)
         C20 = _d((20,) * 3, ptr=FAKE * 3)
         assert _ttv(A20, b20, 1, C20) == 0 and _plan().startswith("ttv slab")
+        # n_lo of 32..63: whole dense slabs (36^5, mode 2) go to the slab
+        # kernel; slabs too long for it (37x600, three of them) or a lo with
+        # gaps stay on the col kernel
+        A36 = _d((36,) * 5)
+        b36 = _d((36,), ptr=FAKE * 2)
+        C36 = _d((36,) * 4, ptr=FAKE * 3)
+        assert _ttv(A36, b36, 2, C36) == 0 and _plan().startswith("ttv slab") and "n_lo=36" in _plan()
+        Ak = _d((37, 600, 3))
+        bk = _d((600,), ptr=FAKE * 2)
+        Ck = _d((37, 3), ptr=FAKE * 3)
+        assert _ttv(Ak, bk, 2, Ck) == 0 and _plan().startswith("ttv col") and "ksplit=" in _plan()
+        Ag = _d((40, 30, 3000), strides=(2, 80, 2400))
+        bg = _d((30,), ptr=FAKE * 2)
+        Cg = _d((40, 3000), ptr=FAKE * 3)
+        assert _ttv(Ag, bg, 2, Cg) == 0 and _plan().startswith("ttv col") and "n_lo=40" in _plan()
         # a C layout that does not follow A's: the dims do not merge, short lo
         # (13 < 32): one fiber per output
         A = _d((13,) * 4)

@@ -2,7 +2,8 @@
 oracle; each case asserts the regime its plan names: the col kernel with one
 wave per (lo tile, hi) unit and all k rows in flight (kr = 8..64, ragged lo,
 vector widths 1/2/4), the col kernel with k split over the waves, with a grid
-split over k, the fiber kernel for contiguous k-fibers and the slab kernel."""
+split over k, the fiber kernel for contiguous k-fibers and the slab kernel
+(n_lo up to 63, b staged in LDS with whole slabs)."""
 import zlib
 
 import numpy as np
@@ -27,11 +28,15 @@ def T():
 REGIMES = [
     ((64, 13, 5000), None, 2, ["ttv col", "kr=16"]),
     ((70, 13, 5000), None, 2, ["ttv col", "kr=16"]),          # ragged lo tile
-    ((33, 7, 9000), None, 2, ["ttv col", "kr=8"]),            # odd lo: scalar loads
+    ((65, 7, 9000), None, 2, ["ttv col", "kr=8"]),            # odd lo: scalar loads
     ((129, 60, 1000), [1, 2, 3], 2, ["ttv col", "kr=0"]),     # too few units: k split over waves
-    ((40, 30, 6000), None, 2, ["ttv col"]),
+    ((72, 30, 3000), None, 2, ["ttv col"]),
+    ((40, 30, 1500), None, 2, ["ttv col"]),                  # n_lo 32..63, too few slabs
+    ((36, 36, 3000), None, 2, ["ttv slab"]),                 # n_lo 32..63, whole slabs
+    ((63, 17, 2500), [1, 2, 3], 2, ["ttv slab"]),
     ((100, 3, 20000), [1, 2, 3], 2, ["ttv col", "kr=8"]),
-    ((5000, 33, 40), [3, 2, 1], 2, ["ttv col"]),              # last-order
+    ((5000, 33, 70), [3, 2, 1], 2, ["ttv col"]),              # last-order
+    ((3000, 33, 40), [3, 2, 1], 2, ["ttv slab"]),             # last-order, C strided along lo
     ((37, 600, 3), None, 2, ["ttv col", "ksplit="]),
     ((8, 50, 9000), None, 2, ["ttv slab"]),
     ((300, 4000), None, 1, ["ttv fiber"]),                   # contiguous fibers of 300
