@@ -406,6 +406,11 @@ static int run_ttv(const Ten& a, const Ten& b, int mi, const Ten& c, hipStream_t
             int64_t want_blocks = std::min<int64_t>(2048, P.n_hi);
             int64_t smax = std::max<int64_t>(1, P.n_hi / want_blocks);
             S = std::max<int64_t>(1, std::min(S, smax));
+            // a multiple of slabs that spans whole 16-byte units, so that every
+            // workgroup's run starts aligned and is copied with 16-byte loads
+            const int64_t sb = slab * es;
+            const int64_t unit = 16 / (sb % 16 == 0 ? 16 : sb % 8 == 0 ? 8 : sb % 4 == 0 ? 4 : sb % 2 == 0 ? 2 : 1);
+            if (S >= unit) S -= S % unit;
         } else {
             S = 1;
             kc = std::max<int64_t>(1, cap / P.n_lo);

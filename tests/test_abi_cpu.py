@@ -85,6 +85,16 @@ def test_ttv_regimes():
         b20 = _d((20,), ptr=FAKE * 2)
         C20 = _d((20,) * 3, ptr=FAKE * 3)
         assert _ttv(A20, b20, 1, C20) == 0 and _plan().startswith("ttv slab")
+        # a workgroup's slabs span whole 16-byte units (13^7, mode 1: 52-byte
+        # FP32 slabs in multiples of four), so every run is copied with
+        # 16-byte loads
+        for dt, es in ((_lib.F32, 4), (_lib.F64, 8)):
+            A13 = _d((13,) * 7, dt)
+            b13 = _d((13,), dt, ptr=FAKE * 2)
+            C13 = _d((13,) * 6, dt, ptr=FAKE * 3)
+            assert _ttv(A13, b13, 1, C13) == 0 and _plan().startswith("ttv slab")
+            slabs = int(re.search(r"slabs=(\d+)", _plan()).group(1))
+            assert slabs > 1 and (slabs * 13 * es) % 16 == 0, _plan()
         # n_lo of 32..63: whole dense slabs (36^5, mode 2) go to the slab
         # kernel; slabs too long for it (37x600, three of them) or a lo with
         # gaps stay on the col kernel
