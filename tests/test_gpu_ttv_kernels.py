@@ -42,6 +42,7 @@ REGIMES = [
     ((300, 4000), None, 1, ["ttv fiber"]),                   # contiguous fibers of 300
     ((45, 70, 90), [3, 1, 2], 3, ["ttv fiber"]),            # last mode stored first
     ((20, 9000), None, 1, ["ttv slab"]),                     # short fibers stay on slabs
+    ((13, 40000), None, 1, ["ttv slab"]),                    # slab count rounded to whole 16-byte units
 ]
 
 
