@@ -3,9 +3,18 @@ benchmark times: the order-p sweep (406^3, 90^4, 36^5, 20^6, 13^7; TTV and
 TTM with m = 16, 64, 256 in every mode, outputs in the benchmark's layouts)
 and the (96,80,64,48) x (64,48,120) TTT, with the shipped kernel table loaded
 as the benchmark loads it, so every TTM/TTT call runs the kernel and tile the
-benchmark times.  The oracle computes sampled outputs one by one, each from a
-view of the inputs that keeps a single index in every free mode.  The
-tolerance (1e-12 FP64, 1e-5 FP32) is applied to the sampled set."""
+benchmark times.
+
+Complete comparisons: every TTV output and every TTM (m = 16) output of the
+sweep, for every p, mode, layout and both dtypes, written into outputs
+filled with NaN beforehand (an output the kernel skips fails), and every
+output of the full TTT in FP32, BF16 and FP16 for the N(0,1) case and its
+x1e3 variant.  Sampled comparisons: TTM with m = 64 and 256, where the oracle
+computes sampled output fibers one by one, each from a view of the inputs
+that keeps a single index in every free mode.  Tolerances: 1e-12 FP64, 1e-5
+FP32 and 16-bit kernel-only (same rounded inputs), 2e-2 normwise end to end
+for 16-bit inputs."""
+import functools
 import os
 
 import numpy as np
@@ -13,7 +22,7 @@ import pytest
 
 import oracle
 import synth
-from _util import assert_close, round_to, to_gpu, to_np
+from _util import TOL, assert_close, assert_close16, round_to, to_gpu, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -43,8 +52,58 @@ def _one(X, idx, keep):
     return X[sl]
 
 
+def _nan_out(T, shape, layout, dtype):
+    import torch
+    C = T.empty(shape, layout, torch.float64 if dtype == "f64" else torch.float32, "cuda")
+    C.fill_(float("nan"))
+    return C
+
+
+@functools.lru_cache(maxsize=2)
+def _sweep_rounded(p, dtype):
+    return round_to(synth.sweep_tensor(p), dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("p", [3, 4, 5, 6, 7])
-def test_sweep_ttv_ttm_sampled(T, p):
+def test_sweep_ttv_ttm16_complete(T, p, dtype):
+    """Every output of TTV and of TTM with m = 16, every mode, both layouts."""
+    print("fullsize complete p=%d %s" % (p, dtype), flush=True)
+    X = synth.sweep_tensor(p)
+    n = X.shape[0]
+    Xr = _sweep_rounded(p, dtype)
+    Xo = oracle.materialize(Xr)
+    tol = TOL[dtype]
+    b, B = synth.sweep_operands(n, 16)
+    br, Br = round_to(b, dtype), round_to(B, dtype)
+    bd, Bd = to_gpu(b, None, dtype), to_gpu(B, [2, 1], dtype)
+    ref_v = {q: np.asarray(oracle.ttv(Xo, br, q)) for q in range(1, p + 1)}
+    ref_m = {}
+    for lname, lay in (("first", list(range(1, p + 1))), ("last", list(range(p, 0, -1)))):
+        A = to_gpu(X, lay, dtype)
+        for q in range(1, p + 1):
+            clay = [r if r < q else r - 1 for r in lay if r != q]
+            Cv = _nan_out(T, (n,) * (p - 1), clay, dtype)
+            plan = T.plan(T.ttv, A, bd, q, out=Cv)
+            T.ttv(A, bd, q, out=Cv)
+            assert_close(to_np(Cv), ref_v[q], tol, "ttv p=%d %s q=%d %s (%s)" % (p, lname, q, dtype, plan))
+            del Cv
+            if q not in ref_m:
+                ref_m[q] = np.asarray(oracle.ttm(Xo, Br, q))
+            shape = [n] * p
+            shape[q - 1] = 16
+            Cm = _nan_out(T, shape, lay, dtype)
+            plan = T.plan(T.ttm, A, Bd, q, out=Cm)
+            assert "autotuned" in plan, plan
+            T.ttm(A, Bd, q, out=Cm)
+            assert_close(to_np(Cm), ref_m[q], tol, "ttm p=%d %s q=%d m=16 %s (%s)" % (p, lname, q, dtype, plan))
+            del Cm
+        del A
+
+
+@pytest.mark.parametrize("p", [3, 4, 5, 6, 7])
+def test_sweep_ttm_sampled(T, p):
+    """TTM with m = 64 and 256: sampled output fibers."""
     print("fullsize sweep p=%d" % p, flush=True)
     X = synth.sweep_tensor(p)
     n = X.shape[0]
@@ -55,17 +114,7 @@ def test_sweep_ttv_ttm_sampled(T, p):
         for lname, lay in (("first", list(range(1, p + 1))), ("last", list(range(p, 0, -1)))):
             A = to_gpu(X, lay, dtype)
             for q in range(1, p + 1):
-                b, _ = synth.sweep_operands(n, 16)
-                br = round_to(b, dtype)
-                Cv = to_np(T.ttv(A, to_gpu(b, None, dtype), q))
-                got_v, ref_v = [], []
-                for _ in range(SAMPLES):
-                    idx = [int(v) for v in g.integers(0, n, p)]
-                    view = oracle.materialize(_one(Xr, idx, {q - 1}))
-                    ref_v.append(float(np.asarray(oracle.ttv(view, br, q)).reshape(-1)[0]))
-                    got_v.append(Cv[tuple(i for r, i in enumerate(idx) if r != q - 1)])
-                assert_close(np.array(got_v), np.array(ref_v), tol, "ttv p=%d %s q=%d %s" % (p, lname, q, dtype))
-                for m in (16, 64, 256):
+                for m in (64, 256):
                     _, B = synth.sweep_operands(n, m)
                     Br = round_to(B, dtype)
                     Bd = to_gpu(B, [2, 1], dtype)  # row-major, as the benchmark allocates it
@@ -85,19 +134,33 @@ def test_sweep_ttv_ttm_sampled(T, p):
             del A
 
 
-@pytest.mark.parametrize("alay", ["first", "last", "perm3142"])
-def test_ttt_fullsize_sampled(T, alay):
-    X, Y = synth.ttt_case()
-    g = synth.rng(41, 0)
-    for dtype in ("f32", "bf16"):
-        Xr, Yr = round_to(X, dtype), round_to(Y, dtype)
-        C = to_np(T.ttt(to_gpu(X, synth.TTT_A_LAYOUTS[alay], dtype), to_gpu(Y, None, dtype), 2,
-                        synth.TTT_PHI, synth.TTT_PSI))
-        got, ref = [], []
-        for _ in range(SAMPLES):
-            i1, i2, j = int(g.integers(96)), int(g.integers(80)), int(g.integers(120))
-            a = oracle.materialize(Xr[i1:i1 + 1, i2:i2 + 1, :, :])
-            bb = oracle.materialize(Yr[:, :, j:j + 1])
-            ref.append(float(np.asarray(oracle.ttt(a, bb, 2, synth.TTT_PHI, synth.TTT_PSI)).reshape(-1)[0]))
-            got.append(C[i1, i2, j])
-        assert_close(np.array(got), np.array(ref), 1e-5, "ttt full size A=%s %s (kernel)" % (alay, dtype))
+@functools.lru_cache(maxsize=8)
+def _ttt_ref(scale, dtype):
+    """Oracle on the inputs rounded to dtype ('orig': unrounded, 'abs': the
+    contraction over absolute values)."""
+    X, Y = synth.ttt_case(scale=scale)
+    if dtype == "abs":
+        X, Y = np.abs(X), np.abs(Y)
+    elif dtype != "orig":
+        X, Y = round_to(X, dtype), round_to(Y, dtype)
+    return np.asarray(oracle.ttt(oracle.materialize(X), oracle.materialize(Y), 2, synth.TTT_PHI, synth.TTT_PSI))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
+@pytest.mark.parametrize("scale", [1.0, 1e3], ids=["n01", "x1e3"])
+def test_ttt_fullsize_complete(T, scale, dtype):
+    """Every output of the full TTT in the three A layouts, into NaN-filled C."""
+    print("fullsize ttt scale=%g %s" % (scale, dtype), flush=True)
+    X, Y = synth.ttt_case(scale=scale)
+    ref = _ttt_ref(scale, dtype)
+    Bd = to_gpu(Y, None, dtype)
+    for alay in ("first", "last", "perm3142"):
+        Ad = to_gpu(X, synth.TTT_A_LAYOUTS[alay], dtype)
+        C = _nan_out(T, (96, 80, 120), None, dtype)
+        plan = T.plan(T.ttt, Ad, Bd, 2, synth.TTT_PHI, synth.TTT_PSI, out=C)
+        T.ttt(Ad, Bd, 2, synth.TTT_PHI, synth.TTT_PSI, out=C)
+        got = to_np(C)
+        what = "ttt full size scale=%g A=%s %s (%s)" % (scale, alay, dtype, plan)
+        assert_close(got, ref, TOL["f32"], what + " (kernel)")
+        if dtype != "f32":
+            assert_close16(got, _ttt_ref(scale, "orig"), _ttt_ref(scale, "abs"), TOL[dtype], what)
