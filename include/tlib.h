@@ -28,13 +28,18 @@
  * norm accumulate and return FP64 for every input dtype.
  *
  * Ownership.  The caller owns every buffer.  The library never allocates or
- * frees caller-visible memory; the small per-stream workspace it keeps for
- * reduction partials is its own.  Host arrays (extents, strides, layout, phi,
- * psi, tau) are read during the call only.
+ * frees caller-visible memory.  It keeps one workspace per (device, stream)
+ * for reduction and split-K partials and for the intermediate of a two-TTM
+ * chain (see tlib_workspace_reserve); host arrays (extents, strides, layout,
+ * phi, psi, tau) are read during the call only.
  *
  * Synchronisation.  Arguments are validated on the host before anything is
  * launched.  Kernels are enqueued on `stream` (a hipStream_t; NULL is the
- * default stream) and the call returns without waiting for them.  C is
+ * default stream) and the call returns without waiting for them: no entry
+ * point synchronises, frees memory or grows the workspace (the one exception
+ * is the first call of a new call shape with autotuning on, see
+ * tlib_set_autotune).  Every call can therefore be captured in a HIP graph
+ * once the stream's workspace exists and is large enough.  C is
  * overwritten, never accumulated into.  Calls on one stream run in order;
  * calls on different streams may overlap.
  *
@@ -65,7 +70,7 @@ enum {
     TLIB_EDTYPE = 4,  /* unsupported dtype, or operands / output of the wrong dtype */
     TLIB_EALIAS = 5,  /* the output overlaps an input (add/scale may run in place, see there) */
     TLIB_ESTRIDE = 6, /* the output's strides may map two multi-indices to one address */
-    TLIB_ENOMEM = 7,  /* the library's workspace could not be allocated */
+    TLIB_ENOMEM = 7,  /* the stream's workspace is too small (or could not be allocated) */
     TLIB_EHIP = 8     /* a HIP call or kernel launch failed */
 };
 
@@ -101,8 +106,8 @@ int tlib_ttm(const tlib_tensor* A, const tlib_tensor* B, int32_t m,
  * replaced by n'_a, n'_b, A's dtype, any injective strides, no overlap with
  * an input.  Without writing A x_a Ua when n'_a, n'_b <= 32 and n_a, n_b <=
  * 256 (the result is the same product summed in another order); otherwise
- * two TTMs through an intermediate held in the library's per-stream
- * workspace (TLIB_ENOMEM if it cannot be allocated).  16-bit inputs:
+ * two TTMs through an intermediate held in the stream's workspace
+ * (TLIB_ENOMEM if it is too small).  16-bit inputs:
  * TLIB_EDTYPE (use two tlib_ttm calls). */
 int tlib_ttm2(const tlib_tensor* A, const tlib_tensor* Ua, int32_t a, const tlib_tensor* Ub,
               int32_t b, const tlib_tensor* C, void* stream);
@@ -152,10 +157,10 @@ int tlib_transpose(const tlib_tensor* A, const int32_t* tau, const tlib_tensor* 
  * vector of length n_k with A's dtype, any stride.  c: order 1, length n_r,
  * FP64 for FP64 A and FP32 otherwise; it must not overlap A or a vector.
  * Accumulates in FP64 in a fixed order (bitwise reproducible) and rounds once
- * to c's dtype.  Uses the library's per-stream workspace (16 bytes per index
- * of the modes outside the tile positions plus the partial sums); returns
- * TLIB_ENOMEM if it cannot be allocated and TLIB_EINVAL if A has more than
- * 2^31 tile positions or 2^30 row entries outside r. */
+ * to c's dtype.  Uses the stream's workspace (16 bytes per index of the
+ * modes outside the tile positions plus the partial sums; TLIB_ENOMEM if it
+ * is too small); TLIB_EINVAL if A has more than 2^31 tile positions or 2^30
+ * row entries outside r. */
 int tlib_times_vectors(const tlib_tensor* A, const tlib_tensor* const* us, int32_t r,
                        const tlib_tensor* c, void* stream);
 
@@ -201,9 +206,12 @@ int tlib_batch_run(const void* table_dev, int32_t grid, void* stream);
  * and stay valid until the request completes.  C gives the result's shape and
  * strides or layout; with C->data == NULL the server places the result in its
  * arena (released at completion unless keep_results), otherwise it writes to
- * C->data.  Arguments are validated when the request runs; a failed request
- * is counted in the statistics' `errors`.  Returns TLIB_ENOMEM if the result
- * can never fit the arena.  *rid receives the request id.
+ * C->data.  Arguments are validated at submission by tlib_request_check (an
+ * invalid request returns its error code and is not queued); a request whose
+ * launch fails is counted in the statistics' `errors`.  Returns TLIB_ENOMEM
+ * if the result can never fit the arena.  *rid receives the request id.
+ * Each slot's stream gets a workspace of TLIB_WORKSPACE_DEFAULT_BYTES at
+ * creation; a request that needs more fails with TLIB_ENOMEM.
  * tlib_server_result: the output descriptor and error code of a completed
  * request (keep_results servers only; pointers valid until destroy).
  * tlib_server_drain waits until nothing is pending or running.
@@ -217,6 +225,11 @@ typedef struct {
 
 tlib_server* tlib_server_create(int32_t device, size_t output_budget, int32_t slots, int32_t group_max,
                                 int64_t group_macs, int32_t keep_results);
+/* Validate one request without running it (the checks of tlib_ttv, tlib_ttm
+ * or tlib_ttt, every descriptor read only after its order and pointers are
+ * checked); C->data may be NULL (a result the server places).  Host only. */
+int tlib_request_check(int32_t op, const tlib_tensor* A, const tlib_tensor* B, int32_t mode, int32_t q,
+                       const int32_t* phi, const int32_t* psi, const tlib_tensor* C);
 int tlib_server_submit(tlib_server* s, int32_t op, const tlib_tensor* A, const tlib_tensor* B, int32_t mode,
                        int32_t q, const int32_t* phi, const int32_t* psi, const tlib_tensor* C, int64_t* rid);
 int tlib_server_drain(tlib_server* s, double timeout_s);
@@ -224,6 +237,29 @@ int tlib_server_stats(tlib_server* s, tlib_server_stats_t* out);
 int tlib_server_result(tlib_server* s, int64_t rid, tlib_tensor* out, int32_t* err);
 void tlib_server_reset_stats(tlib_server* s);
 void tlib_server_destroy(tlib_server* s);
+
+/* ---- Workspace -------------------------------------------------------------
+ * Scratch that some calls need (reduction partials of inner/norm, split-K
+ * partials of TTM/TTT, k-split partials of TTV, tables and partials of
+ * times_vectors, the intermediate of a ttm2 chain) comes from one device
+ * buffer per (device, stream); a call uses it from its start, so calls on the
+ * same stream share it in stream order.  The buffer is created by
+ * tlib_workspace_reserve, or else by the first call on the stream that needs
+ * scratch while the stream is not capturing a graph, with
+ * max(that call's need, TLIB_WORKSPACE_DEFAULT_BYTES) bytes.  A call that needs
+ * more than the buffer holds, or that needs scratch on a capturing stream
+ * without one, returns TLIB_ENOMEM before launching anything.
+ * tlib_workspace_reserve(stream, bytes): make the stream's buffer at least
+ *   `bytes` (current device; not on a capturing stream: TLIB_EINVAL).  A
+ *   smaller buffer it replaces is kept until tlib_workspace_release, so graphs
+ *   captured with it stay valid.  Does not wait for the stream.
+ * tlib_workspace_size(stream): bytes of the stream's buffer (0 if none).
+ * tlib_workspace_release(stream): wait for the stream, then free its buffers.
+ *   Graphs captured from calls on the stream must not be replayed afterwards. */
+#define TLIB_WORKSPACE_DEFAULT_BYTES ((size_t)256 << 20)
+int tlib_workspace_reserve(void* stream, size_t bytes);
+size_t tlib_workspace_size(void* stream);
+int tlib_workspace_release(void* stream);
 
 /* Stride tuple from shape and 1-based layout (Sec. 3.1 Eq. stride.tuple.permutation),
  * layout NULL = first-order.  Host only; writes order values to strides_out. */

@@ -22,6 +22,7 @@ __all__ = [
     "ttv", "ttm", "ttt", "inner", "norm", "add", "scale", "transpose", "times_tensor",
     "times_vectors", "strides", "layout_of", "empty", "TlibError", "plan", "hopm", "tucker",
     "set_autotune", "autotune_entries", "autotune_clear", "autotune_save", "autotune_load",
+    "workspace_reserve", "workspace_size", "workspace_release",
 ]
 
 _torch = None
@@ -289,6 +290,27 @@ def autotune_save(path: str) -> None:
 def autotune_load(path: str) -> None:
     """Add the entries of a saved autotuning table."""
     _lib.check(_lib.lib().tlib_autotune_load(str(path).encode()))
+
+
+def _cur_stream(device=None) -> ctypes.c_void_p:
+    torch = _t()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def workspace_reserve(nbytes: int, device=None) -> None:
+    """Make the current stream's workspace at least `nbytes` (not while the
+    stream is capturing a graph)."""
+    _lib.check(_lib.lib().tlib_workspace_reserve(_cur_stream(device), int(nbytes)))
+
+
+def workspace_size(device=None) -> int:
+    """Bytes of the current stream's workspace (0 before its first use)."""
+    return int(_lib.lib().tlib_workspace_size(_cur_stream(device)))
+
+
+def workspace_release(device=None) -> None:
+    """Wait for the current stream and free its workspace."""
+    _lib.check(_lib.lib().tlib_workspace_release(_cur_stream(device)))
 
 
 from .drivers import hopm, tucker  # noqa: E402

@@ -18,11 +18,11 @@ MAX_ORDER = 16
 EXPORTS = (
     "tlib_ttv", "tlib_ttm", "tlib_ttm2", "tlib_ttt", "tlib_inner", "tlib_norm", "tlib_add", "tlib_scale",
     "tlib_transpose", "tlib_times_vectors", "tlib_batch_table_bytes", "tlib_batch_plan", "tlib_batch_run",
-    "tlib_server_create", "tlib_server_submit", "tlib_server_drain", "tlib_server_stats",
+    "tlib_request_check", "tlib_server_create", "tlib_server_submit", "tlib_server_drain", "tlib_server_stats",
     "tlib_server_result", "tlib_server_reset_stats", "tlib_server_destroy",
     "tlib_strides_from_layout", "tlib_last_error", "tlib_strerror", "tlib_set_plan_only",
     "tlib_last_plan", "tlib_set_autotune", "tlib_autotune_entries", "tlib_autotune_clear", "tlib_autotune_save",
-    "tlib_autotune_load", "tlib_version",
+    "tlib_autotune_load", "tlib_version", "tlib_workspace_reserve", "tlib_workspace_size", "tlib_workspace_release",
 )
 
 
@@ -92,6 +92,14 @@ def lib():
         L.tlib_batch_plan.restype = ctypes.c_int
         L.tlib_batch_run.argtypes = [vp, ctypes.c_int32, vp]
         L.tlib_batch_run.restype = ctypes.c_int
+        L.tlib_request_check.argtypes = [ctypes.c_int32, P, P, ctypes.c_int32, ctypes.c_int32, i32p, i32p, P]
+        L.tlib_request_check.restype = ctypes.c_int
+        L.tlib_workspace_reserve.argtypes = [vp, ctypes.c_size_t]
+        L.tlib_workspace_reserve.restype = ctypes.c_int
+        L.tlib_workspace_size.argtypes = [vp]
+        L.tlib_workspace_size.restype = ctypes.c_size_t
+        L.tlib_workspace_release.argtypes = [vp]
+        L.tlib_workspace_release.restype = ctypes.c_int
         L.tlib_server_create.argtypes = [ctypes.c_int32, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_int64, ctypes.c_int32]
         L.tlib_server_create.restype = vp

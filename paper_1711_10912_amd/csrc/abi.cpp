@@ -18,6 +18,7 @@
 #include <mutex>
 #include <string>
 #include <utility>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -225,46 +226,81 @@ static int check_output(const Ten& c, const char* name) {
 }
 
 // ------------------------------------------------------------------ workspace
+//
+// One device buffer per (device, stream) holds reduction and split-K
+// partials and the intermediate of a two-TTM chain.  Calls on one stream run
+// in stream order, so every call may use the whole buffer from its start.
+// The buffer is allocated by tlib_workspace_reserve, or by the first call on
+// the stream that needs scratch while the stream is not capturing (then to
+// max(need, TLIB_WORKSPACE_DEFAULT_BYTES)).  Entry points never free, grow or
+// wait on it: a call that needs more than the buffer holds fails with
+// TLIB_ENOMEM before launching anything.  A buffer replaced by a larger
+// reserve is kept until tlib_workspace_release, so graphs captured with it
+// stay valid.
 
 namespace {
-struct WsEntry {
-    void* ptr = nullptr;
+struct WsBuf {
+    char* ptr = nullptr;
     size_t bytes = 0;
+    std::vector<void*> retired;  // replaced buffers, freed by tlib_workspace_release
 };
 std::mutex g_ws_mu;
-std::map<std::pair<int, hipStream_t>, WsEntry> g_ws;
+std::map<std::pair<int, hipStream_t>, WsBuf> g_ws;
+
+bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+}
 }  // namespace
 
-static void* workspace_slot(hipStream_t s, size_t bytes, int slot) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-    std::lock_guard<std::mutex> lk(g_ws_mu);
-    WsEntry& e = g_ws[{dev * 2 + slot, s}];
-    if (e.bytes >= bytes && e.ptr) return e.ptr;
-    if (e.ptr) {
-        // kernels already queued on this stream may still read the old buffer
-        if (hipStreamSynchronize(s) != hipSuccess) return nullptr;
-        (void)hipFree(e.ptr);
-        e.ptr = nullptr;
-        e.bytes = 0;
+static constexpr size_t WS_ALIGN = 256;
+static size_t ws_round(size_t b) { return (b + WS_ALIGN - 1) / WS_ALIGN * WS_ALIGN; }
+
+void* WsCtx::take(size_t bytes) {
+    bytes = ws_round(bytes);
+    if (bytes == 0) return base ? base + used : nullptr;
+    if (!base) {
+        if (fixed) return nullptr;
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        WsBuf& e = g_ws[{dev, s}];
+        if (!e.ptr) {
+            if (capturing(s)) return nullptr;  // no allocation while a graph is captured
+            const size_t want = std::max({ws_round(hint), used + bytes, size_t(TLIB_WORKSPACE_DEFAULT_BYTES)});
+            void* p = nullptr;
+            if (hipMalloc(&p, want) != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+            e.ptr = static_cast<char*>(p);
+            e.bytes = want;
+        }
+        base = e.ptr;
+        size = e.bytes;
     }
-    size_t want = std::max<size_t>(bytes, size_t(1) << 20);
-    void* p = nullptr;
-    if (hipMalloc(&p, want) != hipSuccess) {
-        (void)hipGetLastError();
-        return nullptr;
-    }
-    e.ptr = p;
-    e.bytes = want;
+    if (used + bytes > size) return nullptr;
+    void* p = base + used;
+    used += bytes;
     return p;
 }
 
-void* workspace(hipStream_t s, size_t bytes) { return workspace_slot(s, bytes, 0); }
-void* workspace2(hipStream_t s, size_t bytes) { return workspace_slot(s, bytes, 1); }
+// Record the scratch a planned launch takes (plan-only probes read it).
+void WsCtx::need(size_t bytes) { peak = std::max(peak, used + ws_round(bytes)); }
+
+static int ws_fail(const WsCtx& ws, size_t bytes, const char* op) {
+    if (ws.fixed)
+        return fail(TLIB_ENOMEM, "%s: needs %zu bytes of scratch beyond the %zu of the static buffer", op, bytes,
+                    ws.size - ws.used);
+    return fail(TLIB_ENOMEM,
+                "%s: needs %zu bytes of workspace at offset %zu; the stream's workspace holds %zu bytes (reserve "
+                "more with tlib_workspace_reserve before the call, outside graph capture)",
+                op, bytes, ws.used, ws.size);
+}
 
 // ------------------------------------------------------------------ TTV planning
 
-static int run_ttv(const Ten& a, const Ten& b, int mi, const Ten& c, hipStream_t s) {
+static int run_ttv(const Ten& a, const Ten& b, int mi, const Ten& c, hipStream_t s, WsCtx& wsc) {
     Dim d[MAXP];
     int nd = 0;
     for (int r = 0, k = 0; r < a.p; ++r) {
@@ -378,14 +414,15 @@ static int run_ttv(const Ten& a, const Ten& b, int mi, const Ten& c, hipStream_t
                   dname(a.dtype), (long long)P.n_lo, (long long)P.n_k, (long long)P.n_hi,
                   (long long)P.sA_lo, (long long)P.sA_k, (long long)P.sA_hi, (long long)P.sC_lo,
                   (long long)P.sC_hi, P.gh.nd, vec, ks, kr, (long long)(kr ? (nb + 3) / 4 : nb * ks));
+        if (!kr) wsc.need(wsb);
         if (g_plan_only) return TLIB_OK;
         if (kr) {
             int rc = launch_ttv_colw(a.dtype, P, vec, kr, s);
             return rc ? fail(rc, "ttv: launch failed") : TLIB_OK;
         }
         if (ks > 1) {
-            ws = workspace(s, wsb);
-            if (!ws) return fail(TLIB_ENOMEM, "ttv: workspace of %zu bytes", wsb);
+            ws = wsc.take(wsb);
+            if (!ws) return ws_fail(wsc, wsb, "ttv");
         }
         int rc = launch_ttv_col(a.dtype, P, vec, ks, ws, s);
         return rc ? fail(rc, "ttv: launch failed") : TLIB_OK;
@@ -514,7 +551,7 @@ static int tuned(const std::string& key, const int* cands, int nc, hipStream_t s
     int nl = 0;
     for (int i = 0; i < nc && nl < MAXC; ++i) {
         const int rc = run(cands[i]);
-        if (rc == PICK_NA) continue;
+        if (rc == PICK_NA || rc == TLIB_ENOMEM) continue;  // not applicable, or more scratch than the stream holds
         if (rc != TLIB_OK) return rc;
         live[nl] = cands[i];
         tmin[nl++] = 0.f;
@@ -552,7 +589,7 @@ static int tuned(const std::string& key, const int* cands, int nc, hipStream_t s
 // dm: M-group dims with strides (X, C); dn: N-group (Y, C); dk: K-group (X, Y).
 // tile_force >= 0 replaces the tile heuristic (autotuning candidates).
 static int run_gemm(int dtype, const void* X, const void* Y, void* C, Dim* dm, int ndm, Dim* dn,
-                    int ndn, Dim* dk, int ndk, const char* op, hipStream_t s, int tile_force = -1) {
+                    int ndn, Dim* dk, int ndk, const char* op, hipStream_t s, WsCtx& wsc, int tile_force = -1) {
     // Dims are stored with strides in slots 0/1 as documented above.
     int64_t M = 1, N = 1, K = 1;
     for (int i = 0; i < ndm; ++i) M *= dm[i].n;
@@ -673,10 +710,11 @@ static int run_gemm(int dtype, const void* X, const void* Y, void* C, Dim* dm, i
                   "cvec=%d yvec=%d kvec=%d ksplit=%d tiles=%lld",
                   op, dname(dtype), (long long)M, (long long)N, (long long)K, ndm, ndn, ndk, ts.bm,
                   ts.bn, P.x_kfast, P.y_kfast, P.c_vec, P.y_vec, P.kvec, P.ksplit, (long long)nt);
+        wsc.need(wsb);
         if (g_plan_only) return TLIB_OK;
         if (P.ksplit > 1) {
-            P.part = workspace(s, wsb);
-            if (!P.part) return fail(TLIB_ENOMEM, "%s: workspace of %zu bytes", op, wsb);
+            P.part = wsc.take(wsb);
+            if (!P.part) return ws_fail(wsc, wsb, op);
         }
         int rc = launch_gemm(dtype, tile, P, s);
         return rc ? fail(rc, "%s: launch failed", op) : TLIB_OK;
@@ -811,7 +849,9 @@ int tlib_ttv(const tlib_tensor* A, const tlib_tensor* b, int32_t m, const tlib_t
     Ten a, v, c;
     int rc = check_ttv(A, b, m, C, a, v, c);
     if (rc) return rc;
-    return run_ttv(a, v, m - 1, c, hipStream_t(stream));
+    WsCtx ws;
+    ws.s = hipStream_t(stream);
+    return run_ttv(a, v, m - 1, c, hipStream_t(stream), ws);
 }
 
 // One TTM launch.  pick: TTM_PICK_HEUR (planner's rule), TTM_PICK_STREAM
@@ -820,7 +860,7 @@ int tlib_ttv(const tlib_tensor* A, const tlib_tensor* b, int32_t m, const tlib_t
 // GEMM's own tile rule).  Returns PICK_NA when the pick does not apply.
 enum { TTM_PICK_HEUR = -1, TTM_PICK_STREAM = 0, TTM_PICK_ROWS_PLAIN = 1, TTM_PICK_GEMM = 2 };
 
-static int ttm_dispatch(const Ten& a, const Ten& bm, int mi, const Ten& c, int pick, void* stream) {
+static int ttm_dispatch(const Ten& a, const Ten& bm, int mi, const Ten& c, int pick, void* stream, WsCtx& wsc) {
     // Short contraction: the streaming kernels (B resident in LDS, A streamed).
     {
         const int64_t Mr = bm.n[0], Kr = a.n[mi];
@@ -948,7 +988,7 @@ static int ttm_dispatch(const Ten& a, const Ten& bm, int mi, const Ten& c, int p
         if (r != mi) dn[ndn++] = {a.n[r], {a.w[r], c.w[r], 0}};
     Dim dk[1] = {{a.n[mi], {bm.w[1], a.w[mi], 0}}};
     const int tile = pick >= TTM_PICK_GEMM ? pick - TTM_PICK_GEMM : -1;
-    return run_gemm(a.dtype, bm.data, a.data, c.data, dm, 1, dn, ndn, dk, 1, "ttm", hipStream_t(stream),
+    return run_gemm(a.dtype, bm.data, a.data, c.data, dm, 1, dn, ndn, dk, 1, "ttm", hipStream_t(stream), wsc,
                     tile < GT_COUNT ? tile : -1);
 }
 
@@ -1019,8 +1059,12 @@ int tlib_ttm(const tlib_tensor* A, const tlib_tensor* B, int32_t m, const tlib_t
     key_ten(key, a);
     key_ten(key, bm);
     key_ten(key, c);
-    return tuned(key, cands, int(sizeof(cands) / sizeof(cands[0])), hipStream_t(stream),
-                 [&](int pick) { return ttm_dispatch(a, bm, mi, c, pick, stream); });
+    WsCtx ws;
+    ws.s = hipStream_t(stream);
+    return tuned(key, cands, int(sizeof(cands) / sizeof(cands[0])), hipStream_t(stream), [&](int pick) {
+        ws.used = 0;
+        return ttm_dispatch(a, bm, mi, c, pick, stream, ws);
+    });
 }
 
 // Two mode products C = (A x_a Ua) x_b Ub in one pass (Sec. 5.2 Eq. ttm
@@ -1128,12 +1172,31 @@ int tlib_ttm2(const tlib_tensor* A, const tlib_tensor* Ua, int32_t ma, const tli
         }
     }
     const size_t tb = size_t(t.numel()) * size_t(esize(a.dtype));
+    // scratch of the two TTMs (split-K partials), probed by planning them
+    // with a placeholder intermediate; the intermediate comes first
+    size_t part = 0;
+    {
+        const bool po = g_plan_only;
+        g_plan_only = true;
+        t.data = a.data;
+        WsCtx probe;
+        if ((rc = ttm_dispatch(a, ua, ia, t, TTM_PICK_HEUR, stream, probe)) == TLIB_OK)
+            rc = ttm_dispatch(t, ub, ib, c, TTM_PICK_HEUR, stream, probe);
+        g_plan_only = po;
+        if (rc) return rc;
+        part = probe.peak;
+    }
     plan_note("ttm2 chain dtype=%s a=%d b=%d intermediate=%zu bytes", dname(a.dtype), ma, mb, tb);
     if (g_plan_only) return TLIB_OK;
-    t.data = workspace2(s, tb);
-    if (!t.data) return fail(TLIB_ENOMEM, "ttm2: intermediate of %zu bytes", tb);
-    if ((rc = ttm_dispatch(a, ua, ia, t, TTM_PICK_HEUR, stream))) return rc;
-    return ttm_dispatch(t, ub, ib, c, TTM_PICK_HEUR, stream);
+    WsCtx ws;
+    ws.s = s;
+    ws.hint = ws_round(tb) + part;
+    t.data = ws.take(tb);
+    if (!t.data || ws.avail() < part) return ws_fail(ws, ws_round(tb) + part, "ttm2");
+    const size_t mark = ws.used;
+    if ((rc = ttm_dispatch(a, ua, ia, t, TTM_PICK_HEUR, stream, ws))) return rc;
+    ws.used = mark;  // the first product's partials are consumed before the second runs
+    return ttm_dispatch(t, ub, ib, c, TTM_PICK_HEUR, stream, ws);
 }
 
 int tlib_ttt(const tlib_tensor* A, const tlib_tensor* B, int32_t q, const int32_t* phi,
@@ -1163,13 +1226,16 @@ int tlib_ttt(const tlib_tensor* A, const tlib_tensor* B, int32_t q, const int32_
     if ((rc = check_output(c, "C"))) return rc;
     if (overlaps(c, a) || overlaps(c, b)) return fail(TLIB_EALIAS, "ttt: C overlaps an input");
     // GEMM roles: X = A (M = free A modes), Y = B (N = free B modes), K = pairs.
+    WsCtx ws;
+    ws.s = hipStream_t(stream);
     auto run = [&](int tile) {
+        ws.used = 0;
         Dim dm[MAXP], dn[MAXP], dk[MAXP];
         for (int k = 0; k < r; ++k) dm[k] = {a.n[phi[k] - 1], {a.w[phi[k] - 1], c.w[k], 0}};
         for (int k = 0; k < s; ++k) dn[k] = {b.n[psi[k] - 1], {b.w[psi[k] - 1], c.w[r + k], 0}};
         for (int k = 0; k < q; ++k)
             dk[k] = {a.n[phi[r + k] - 1], {a.w[phi[r + k] - 1], b.w[psi[s + k] - 1], 0}};
-        return run_gemm(a.dtype, a.data, b.data, c.data, dm, r, dn, s, dk, q, "ttt", hipStream_t(stream), tile);
+        return run_gemm(a.dtype, a.data, b.data, c.data, dm, r, dn, s, dk, q, "ttt", hipStream_t(stream), ws, tile);
     };
     static const int cands[] = {GT_16x256, GT_64x128, GT_128x128, GT_256x64, GT_64x64, GT_128x64, GT_256x32};
     std::string key = "ttt";
@@ -1183,6 +1249,8 @@ int tlib_ttt(const tlib_tensor* A, const tlib_tensor* B, int32_t q, const int32_
 }
 
 static int run_dot(const Ten& a, const Ten* b, double* out, bool sq, hipStream_t s, const char* op) {
+    WsCtx wsc;
+    wsc.s = s;
     Dim d[MAXP];
     for (int r = 0; r < a.p; ++r) d[r] = {a.n[r], {a.w[r], b ? b->w[r] : a.w[r], 0}};
     int nd = coalesce(d, a.p, 2, 0);
@@ -1192,9 +1260,10 @@ static int run_dot(const Ten& a, const Ten* b, double* out, bool sq, hipStream_t
     size_t wsb = size_t(np) * sizeof(double);
     plan_note("%s dot dtype=%s dims=%d total=%lld partials=%d", op, dname(a.dtype), nd,
               (long long)g.total, np);
+    wsc.need(wsb);
     if (g_plan_only) return TLIB_OK;
-    void* ws = workspace(s, wsb);
-    if (!ws) return fail(TLIB_ENOMEM, "%s: workspace", op);
+    void* ws = wsc.take(wsb);
+    if (!ws) return ws_fail(wsc, wsb, op);
     int rc = launch_dot(a.dtype, a.data, b ? b->data : nullptr, g, out, sq, ws, wsb, s);
     return rc ? fail(rc, "%s: launch failed", op) : TLIB_OK;
 }
@@ -1454,8 +1523,10 @@ int tlib_times_vectors(const tlib_tensor* A, const tlib_tensor* const* us, int32
               (long long)n_out, (long long)n_hi, P.HC, vec ? 1 : 0, P.lin, (long long)(items * hc));
     if (g_plan_only) return TLIB_OK;
     hipStream_t s = hipStream_t(stream);
-    char* ws = static_cast<char*>(workspace(s, wsb));
-    if (!ws) return fail(TLIB_ENOMEM, "times_vectors: workspace of %zu bytes", wsb);
+    WsCtx wsc;
+    wsc.s = s;
+    char* ws = static_cast<char*>(wsc.take(wsb));
+    if (!ws) return ws_fail(wsc, wsb, "times_vectors");
     P.tabw = reinterpret_cast<double*>(ws);
     P.tabo = reinterpret_cast<int64_t*>(ws + ntab * 8);
     P.part = reinterpret_cast<double*>(ws + ntab * 16);
@@ -1480,6 +1551,28 @@ int tlib_transpose(const tlib_tensor* A, const int32_t* tau, const tlib_tensor* 
     if ((rc = check_output(c, "C"))) return rc;
     if (overlaps(c, a)) return fail(TLIB_EALIAS, "transpose: C overlaps A");
     return run_axpby(1.0, a, 0.0, nullptr, c, wa, hipStream_t(stream), "transpose");
+}
+
+int tlib_request_check(int32_t op, const tlib_tensor* A, const tlib_tensor* B, int32_t mode, int32_t q,
+                       const int32_t* phi, const int32_t* psi, const tlib_tensor* C) {
+    begin_call();
+    if (op < 0 || op > 2) return fail(TLIB_EINVAL, "request: unknown op %d", op);
+    if (!A || !B || !C) return fail(TLIB_EINVAL, "request: NULL descriptor");
+    if (op == 2 && (!phi || !psi)) return fail(TLIB_EINVAL, "request: TTT needs phi and psi");
+    // a result the server places later is checked at a stand-in address far
+    // below any device allocation
+    tlib_tensor c = *C;
+    if (!c.data) c.data = reinterpret_cast<void*>(uintptr_t(4096));
+    const bool po = g_plan_only;
+    const std::string plan = g_plan;
+    g_plan_only = true;
+    int rc;
+    if (op == 0) rc = tlib_ttv(A, B, mode, &c, nullptr);
+    else if (op == 1) rc = tlib_ttm(A, B, mode, &c, nullptr);
+    else rc = tlib_ttt(A, B, q, phi, psi, &c, nullptr);
+    g_plan_only = po;
+    g_plan = plan;
+    return rc;
 }
 
 size_t tlib_batch_table_bytes(int32_t n) {
@@ -1548,6 +1641,51 @@ int tlib_strides_from_layout(int32_t order, const int64_t* extents, const int32_
     return TLIB_OK;
 }
 
+int tlib_workspace_reserve(void* stream, size_t bytes) {
+    begin_call();
+    hipStream_t s = hipStream_t(stream);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(TLIB_EHIP, "workspace_reserve: no device");
+    if (capturing(s)) return fail(TLIB_EINVAL, "workspace_reserve: the stream is capturing a graph");
+    bytes = ws_round(std::max<size_t>(bytes, 1));
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    WsBuf& e = g_ws[{dev, s}];
+    if (e.ptr && e.bytes >= bytes) return TLIB_OK;
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(TLIB_ENOMEM, "workspace_reserve: hipMalloc of %zu bytes failed", bytes);
+    }
+    if (e.ptr) e.retired.push_back(e.ptr);  // graphs captured earlier may still use it
+    e.ptr = static_cast<char*>(p);
+    e.bytes = bytes;
+    return TLIB_OK;
+}
+
+size_t tlib_workspace_size(void* stream) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto it = g_ws.find({dev, hipStream_t(stream)});
+    return it == g_ws.end() ? 0 : it->second.bytes;
+}
+
+int tlib_workspace_release(void* stream) {
+    begin_call();
+    hipStream_t s = hipStream_t(stream);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(TLIB_EHIP, "workspace_release: no device");
+    if (capturing(s)) return fail(TLIB_EINVAL, "workspace_release: the stream is capturing a graph");
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto it = g_ws.find({dev, s});
+    if (it == g_ws.end()) return TLIB_OK;
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(TLIB_EHIP, "workspace_release: stream wait failed");
+    for (void* p : it->second.retired) (void)hipFree(p);
+    if (it->second.ptr) (void)hipFree(it->second.ptr);
+    g_ws.erase(it);
+    return TLIB_OK;
+}
+
 const char* tlib_last_error(void) { return g_err.c_str(); }
 
 const char* tlib_strerror(int code) {
@@ -1559,7 +1697,7 @@ const char* tlib_strerror(int code) {
         case TLIB_EDTYPE: return "unsupported or mismatched dtype";
         case TLIB_EALIAS: return "output overlaps an input";
         case TLIB_ESTRIDE: return "output strides overlap";
-        case TLIB_ENOMEM: return "workspace allocation failed";
+        case TLIB_ENOMEM: return "not enough workspace";
         case TLIB_EHIP: return "HIP launch failed";
     }
     return "unknown error";

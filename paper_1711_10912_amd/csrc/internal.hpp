@@ -287,9 +287,20 @@ int launch_axpby_tile(int in_dtype, int out_dtype, double alpha, const void* A, 
                       void* C, const EwTile& t, int b_mode, hipStream_t s);
 
 // ------------------------------------------------------------------ workspace (abi.cpp)
-// Per-(device, stream) scratch for reduction partials; grows on demand.
-void* workspace(hipStream_t s, size_t bytes);
-// A second per-stream buffer (for intermediates that must not share the first)
-void* workspace2(hipStream_t s, size_t bytes);
+// Scratch of one call: the stream's workspace (acquired on the first take),
+// or a fixed buffer the caller brings (`fixed`).  take() hands out 256-byte
+// aligned pieces from the start and returns nullptr when the buffer cannot
+// hold them (or cannot be allocated); it never frees or waits.
+struct WsCtx {
+    hipStream_t s = nullptr;
+    char* base = nullptr;
+    size_t size = 0, used = 0;
+    size_t hint = 0;   // bytes the whole call will take (first allocation size)
+    size_t peak = 0;   // largest used + need() seen (plan-only probes)
+    bool fixed = false;
+    void* take(size_t bytes);
+    void need(size_t bytes);
+    size_t avail() const { return size > used ? size - used : 0; }
+};
 
 }  // namespace tlib

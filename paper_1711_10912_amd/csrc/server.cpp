@@ -293,7 +293,10 @@ tlib_server* tlib_server_create(int32_t device, size_t output_budget, int32_t sl
     S->table_bytes = tlib_batch_table_bytes(group_max);
     S->slots.resize(slots);
     for (auto& s : S->slots) {
+        // each slot's stream gets its workspace now, so that requests never
+        // allocate (or fail for want of scratch) once the server runs
         bool ok = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) == hipSuccess &&
+                  tlib_workspace_reserve((void*)s.stream, TLIB_WORKSPACE_DEFAULT_BYTES) == TLIB_OK &&
                   hipEventCreate(&s.done) == hipSuccess &&
                   hipHostMalloc(&s.tab_host, S->table_bytes, hipHostMallocDefault) == hipSuccess &&
                   hipMalloc(&s.tab_dev, S->table_bytes) == hipSuccess &&
@@ -329,8 +332,11 @@ tlib_server* tlib_server_create(int32_t device, size_t output_budget, int32_t sl
 
 int tlib_server_submit(tlib_server* S, int32_t op, const tlib_tensor* A, const tlib_tensor* B, int32_t mode,
                        int32_t q, const int32_t* phi, const int32_t* psi, const tlib_tensor* C, int64_t* rid) {
-    if (!S || !A || !B || !C || op < 0 || op > 2) return TLIB_EINVAL;
+    if (!S) return TLIB_EINVAL;
     const double t = now_s();
+    // every argument is checked before anything is copied from it
+    const int vrc = tlib_request_check(op, A, B, mode, q, phi, psi, C);
+    if (vrc != TLIB_OK) return vrc;
     Job* j = new Job();
     j->op = op;
     j->mode = mode;
@@ -340,12 +346,8 @@ int tlib_server_submit(tlib_server* S, int32_t op, const tlib_tensor* A, const t
     j->c.set(C);
     j->own_out = C->data == nullptr;
     if (op == 2) {
-        if (!phi || !psi) {
-            delete j;
-            return TLIB_EINVAL;
-        }
-        for (int r = 0; r < A->order && r < TLIB_MAX_ORDER; ++r) j->phi[r] = phi[r];
-        for (int r = 0; r < B->order && r < TLIB_MAX_ORDER; ++r) j->psi[r] = psi[r];
+        for (int r = 0; r < A->order; ++r) j->phi[r] = phi[r];
+        for (int r = 0; r < B->order; ++r) j->psi[r] = psi[r];
     }
     int64_t outs = 1, span = 0;
     for (int r = 0; r < C->order; ++r) {

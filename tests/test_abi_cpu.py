@@ -340,3 +340,55 @@ def test_ewise_regimes():
         Sc = _d((8, 500), _lib.F64, ptr=FAKE * 2)
         assert L.tlib_scale(1.0, ctypes.byref(S), ctypes.byref(Sc), None) == 0
         assert "tile" not in _plan()
+
+
+def _req(op, A, B, mode, C, q=0, phi=None, psi=None):
+    L = _lib.lib()
+    pa = _lib.i32_array(phi) if phi is not None else None
+    pb = _lib.i32_array(psi) if psi is not None else None
+    return L.tlib_request_check(op, ctypes.byref(A) if A is not None else None,
+                                ctypes.byref(B) if B is not None else None, mode, q, pa, pb,
+                                ctypes.byref(C) if C is not None else None)
+
+
+def test_request_check_rejects_before_reading():
+    """A served request is validated in full before any descriptor field is
+    copied: order beyond TLIB_MAX_ORDER, mode 0 or past the order, NULL
+    extents, a non-permutation layout and unknown ops are refused with their
+    codes, and a result the server places later (data NULL) is accepted."""
+    A = _d((8, 9, 10))
+    b = _d((9,), ptr=FAKE * 2)
+    C = _lib.desc(0, _lib.F64, (8, 10))
+    assert _req(0, A, b, 2, C) == _lib.OK
+    big = _lib.desc(FAKE, _lib.F64, (2,) * 17)
+    assert _req(0, big, b, 2, C) == _lib.EINVAL
+    assert "order" in _lib.lib().tlib_last_error().decode()
+    assert _req(0, A, b, 0, C) == _lib.EMODE
+    assert _req(0, A, b, 4, C) == _lib.EMODE
+    assert _req(1, A, _d((5, 9), ptr=FAKE * 2), 0, _lib.desc(0, _lib.F64, (8, 5, 10))) == _lib.EMODE
+    noext = _lib.desc(FAKE, _lib.F64, (8, 9, 10))
+    noext.extents = None
+    assert _req(0, noext, b, 2, C) == _lib.EINVAL
+    assert _req(0, _d((8, 9, 10), layout=(1, 1, 2)), b, 2, C) == _lib.EMODE
+    assert _req(3, A, b, 2, C) == _lib.EINVAL
+    assert _req(0, None, b, 2, C) == _lib.EINVAL
+    # TTT: phi / psi must be given and be permutations
+    B = _d((9, 10, 7), ptr=FAKE * 2)
+    Ct = _lib.desc(0, _lib.F64, (8, 7))
+    assert _req(2, A, B, 0, Ct, 2, (1, 2, 3), (3, 1, 2)) == _lib.OK
+    assert _req(2, A, B, 0, Ct, 2, None, (3, 1, 2)) == _lib.EINVAL
+    assert _req(2, A, B, 0, Ct, 2, (1, 2, 2), (3, 1, 2)) == _lib.EMODE
+    assert _req(2, A, B, 0, Ct, 4, (1, 2, 3), (3, 1, 2)) == _lib.EINVAL
+
+
+def test_config3_ttt_plans_split_k():
+    """The (96,80,64,48) x (64,48,120) contraction has few output tiles, so it
+    plans split-K partials (scratch from the stream's workspace)."""
+    L = _lib.lib()
+    with Plan():
+        A = _d((96, 80, 64, 48), _lib.F32)
+        B = _d((64, 48, 120), _lib.F32, ptr=FAKE * 2)
+        C = _d((96, 80, 120), _lib.F32, ptr=FAKE * 3)
+        rc = L.tlib_ttt(ctypes.byref(A), ctypes.byref(B), 2, _lib.i32_array((1, 2, 3, 4)),
+                        _lib.i32_array((3, 1, 2)), ctypes.byref(C), None)
+        assert rc == 0 and int(_plan().split("ksplit=")[1].split()[0]) > 1, _plan()
