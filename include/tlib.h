@@ -311,6 +311,15 @@ void tlib_autotune_clear(void);
 int tlib_autotune_save(const char* path);
 int tlib_autotune_load(const char* path);
 
+/* Plan cache.  tlib_ttv, tlib_ttm and tlib_ttt keep the plan of each call
+ * shape (operation, modes, and per operand its dtype, order, extents,
+ * strides and address modulo 16): a repeated shape skips the
+ * planner and only fills in the data pointers.  Thread-safe; emptied when it
+ * holds 8192 plans and whenever the autotune mode or table changes.  Stats
+ * count the lookups of validated calls since the library was loaded. */
+void tlib_plan_cache_stats(int64_t* entries, int64_t* hits, int64_t* misses);
+void tlib_plan_cache_clear(void);
+
 /* Library version string. */
 const char* tlib_version(void);
 

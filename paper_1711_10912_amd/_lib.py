@@ -22,7 +22,7 @@ EXPORTS = (
     "tlib_server_result", "tlib_server_reset_stats", "tlib_server_destroy",
     "tlib_strides_from_layout", "tlib_last_error", "tlib_strerror", "tlib_set_plan_only",
     "tlib_last_plan", "tlib_set_autotune", "tlib_autotune_entries", "tlib_autotune_clear", "tlib_autotune_save",
-    "tlib_autotune_load", "tlib_version", "tlib_workspace_reserve", "tlib_workspace_size", "tlib_workspace_release",
+    "tlib_autotune_load", "tlib_version", "tlib_plan_cache_stats", "tlib_plan_cache_clear", "tlib_workspace_reserve", "tlib_workspace_size", "tlib_workspace_release",
 )
 
 
@@ -94,6 +94,10 @@ def lib():
         L.tlib_batch_run.restype = ctypes.c_int
         L.tlib_request_check.argtypes = [ctypes.c_int32, P, P, ctypes.c_int32, ctypes.c_int32, i32p, i32p, P]
         L.tlib_request_check.restype = ctypes.c_int
+        L.tlib_plan_cache_stats.argtypes = [i64p, i64p, i64p]
+        L.tlib_plan_cache_stats.restype = None
+        L.tlib_plan_cache_clear.argtypes = []
+        L.tlib_plan_cache_clear.restype = None
         L.tlib_workspace_reserve.argtypes = [vp, ctypes.c_size_t]
         L.tlib_workspace_reserve.restype = ctypes.c_int
         L.tlib_workspace_size.argtypes = [vp]

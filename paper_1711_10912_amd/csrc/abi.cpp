@@ -15,10 +15,14 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
+#include <unordered_map>
 #include <string>
 #include <utility>
 #include <vector>
+
+#include <hip/hip_runtime.h>
 
 #include "internal.hpp"
 
@@ -298,9 +302,136 @@ static int ws_fail(const WsCtx& ws, size_t bytes, const char* op) {
                 op, bytes, ws.used, ws.size);
 }
 
+// ------------------------------------------------------------------ launch records
+//
+// Planning a TTV / TTM / TTT call ends in a Launch: the kernel, its parameter
+// block and launch shape, the scratch it takes and the plan text, with the
+// operand pointers left to be filled in.  exec_launch fills them in and
+// launches.  Records are cached per call shape (plan cache below), so a
+// repeated shape skips planning.
+
+enum LaunchKind {
+    LK_NONE = 0, LK_TTV_COLW, LK_TTV_COL, LK_TTV_SLAB, LK_TTV_FIBER, LK_TTV_GENERIC,
+    LK_GEMM, LK_GEMM_GENERIC, LK_TTM_STREAM, LK_TTM_ROWS
+};
+
+struct Launch {
+    int kind = LK_NONE;
+    int dtype = 0;
+    int i0 = 0, i1 = 0, i2 = 0;  // kernel-specific: vec/ks/kr, slabs/kc, G, tile, fm/mode, ks, grid
+    int xsrc = 0;                // GEMM: X is operand 0 (A) or 1 (B / b) of the call
+    size_t wsb = 0;              // scratch bytes taken from the call's workspace
+    const char* op = "";
+    TtvParams ttv{};
+    Grp go{};
+    GDims gd[3]{};
+    GemmParams gemm{};
+    TtmParams tstr{};
+    TtmRowParams trow{};
+    std::string note;
+};
+
+// in0 = A, in1 = b / B, out = C
+static int exec_launch(const Launch& L, const void* in0, const void* in1, void* out, WsCtx& ws, hipStream_t s) {
+    ws.need(L.wsb);
+    if (g_plan_only) return TLIB_OK;
+    void* w = nullptr;
+    if (L.wsb) {
+        w = ws.take(L.wsb);
+        if (!w) return ws_fail(ws, L.wsb, L.op);
+    }
+    int rc = TLIB_EHIP;
+    if (L.kind >= LK_TTV_COLW && L.kind <= LK_TTV_GENERIC) {
+        TtvParams P = L.ttv;
+        P.A = in0;
+        P.b = in1;
+        P.C = out;
+        switch (L.kind) {
+            case LK_TTV_COLW: rc = launch_ttv_colw(L.dtype, P, L.i0, L.i1, s); break;
+            case LK_TTV_COL: rc = launch_ttv_col(L.dtype, P, L.i0, L.i1, w, s); break;
+            case LK_TTV_SLAB: rc = launch_ttv_slab(L.dtype, P, L.i0, L.i1, s); break;
+            case LK_TTV_FIBER: rc = launch_ttv_fiber(L.dtype, P, L.go, L.i0, s); break;
+            default: rc = launch_ttv_generic(L.dtype, P, L.gd[0], s); break;
+        }
+    } else if (L.kind == LK_GEMM) {
+        GemmParams P = L.gemm;
+        P.X = L.xsrc ? in1 : in0;
+        P.Y = L.xsrc ? in0 : in1;
+        P.C = out;
+        P.part = w;
+        rc = launch_gemm(L.dtype, L.i0, P, s);
+    } else if (L.kind == LK_GEMM_GENERIC) {
+        rc = launch_gemm_generic(L.dtype, L.xsrc ? in1 : in0, L.xsrc ? in0 : in1, out, L.gd[0], L.gd[1], L.gd[2], s);
+    } else if (L.kind == LK_TTM_STREAM) {
+        TtmParams T = L.tstr;
+        T.X = in1;
+        T.Y = in0;
+        T.C = out;
+        rc = launch_ttm_stream(L.dtype, T, L.i0, L.i1, true, L.i2, s);
+    } else if (L.kind == LK_TTM_ROWS) {
+        TtmRowParams R = L.trow;
+        R.X = in1;
+        R.Y = in0;
+        R.C = out;
+        rc = launch_ttm_rows(L.dtype, R, L.i0, L.i1, L.i2, s);
+    }
+    return rc ? fail(rc, "%s: launch failed", L.op) : TLIB_OK;
+}
+
+// ------------------------------------------------------------------ plan cache
+//
+// Launch records keyed by the call shape: operation, modes, and per operand
+// its dtype, order, extents, strides and address modulo 16 (the planner's
+// vector-width decisions read nothing finer).  Guarded by a lock; emptied when
+// full and whenever the autotune table or mode changes (the key does not hold
+// the kernel choice).
+
+namespace {
+std::mutex g_pc_mu;
+std::unordered_map<std::string, std::shared_ptr<const Launch>> g_pc;
+std::atomic<int64_t> g_pc_hits{0}, g_pc_misses{0};
+constexpr size_t PC_MAX = 8192;
+enum { PCK_TTV = 1, PCK_TTM = 2, PCK_TTT = 3 };
+}  // namespace
+
+static void pk(std::string& k, int64_t v) { k.append(reinterpret_cast<const char*>(&v), sizeof(v)); }
+
+static void pk_ten(std::string& k, const Ten& t) {
+    pk(k, int64_t(t.dtype) | (int64_t(t.p) << 8) | (int64_t(uintptr_t(t.data) & 15) << 16));
+    for (int r = 0; r < t.p; ++r) {
+        pk(k, t.n[r]);
+        pk(k, t.w[r]);
+    }
+}
+
+static std::shared_ptr<const Launch> pc_get(const std::string& k) {
+    std::lock_guard<std::mutex> lk(g_pc_mu);
+    auto it = g_pc.find(k);
+    if (it == g_pc.end()) {
+        ++g_pc_misses;
+        return nullptr;
+    }
+    ++g_pc_hits;
+    return it->second;
+}
+
+static void pc_put(const std::string& k, const Launch& L) {
+    auto v = std::make_shared<const Launch>(L);
+    std::lock_guard<std::mutex> lk(g_pc_mu);
+    if (g_pc.size() >= PC_MAX) g_pc.clear();
+    g_pc[k] = std::move(v);
+}
+
+static void pc_clear() {
+    std::lock_guard<std::mutex> lk(g_pc_mu);
+    g_pc.clear();
+}
+
 // ------------------------------------------------------------------ TTV planning
 
-static int run_ttv(const Ten& a, const Ten& b, int mi, const Ten& c, hipStream_t s, WsCtx& wsc) {
+static int plan_ttv(const Ten& a, const Ten& b, int mi, const Ten& c, Launch& L) {
+    L.op = "ttv";
+    L.dtype = a.dtype;
     Dim d[MAXP];
     int nd = 0;
     for (int r = 0, k = 0; r < a.p; ++r) {
@@ -407,25 +538,23 @@ static int run_ttv(const Ten& a, const Ten& b, int mi, const Ten& c, hipStream_t
                     kr = c;
                     break;
                 }
-        void* ws = nullptr;
         size_t wsb = ks > 1 ? size_t(ks) * size_t(outs) * size_t(esize(acc_dtype(a.dtype))) : 0;
         plan_note("ttv col dtype=%s n_lo=%lld n_k=%lld n_hi=%lld sA=(%lld,%lld,%lld) sC=(%lld,%lld) "
                   "hidims=%d vec=%d ksplit=%d kr=%d blocks=%lld",
                   dname(a.dtype), (long long)P.n_lo, (long long)P.n_k, (long long)P.n_hi,
                   (long long)P.sA_lo, (long long)P.sA_k, (long long)P.sA_hi, (long long)P.sC_lo,
                   (long long)P.sC_hi, P.gh.nd, vec, ks, kr, (long long)(kr ? (nb + 3) / 4 : nb * ks));
-        if (!kr) wsc.need(wsb);
-        if (g_plan_only) return TLIB_OK;
+        L.ttv = P;
+        L.i0 = vec;
         if (kr) {
-            int rc = launch_ttv_colw(a.dtype, P, vec, kr, s);
-            return rc ? fail(rc, "ttv: launch failed") : TLIB_OK;
+            L.kind = LK_TTV_COLW;
+            L.i1 = kr;
+        } else {
+            L.kind = LK_TTV_COL;
+            L.i1 = ks;
+            L.wsb = wsb;
         }
-        if (ks > 1) {
-            ws = wsc.take(wsb);
-            if (!ws) return ws_fail(wsc, wsb, "ttv");
-        }
-        int rc = launch_ttv_col(a.dtype, P, vec, ks, ws, s);
-        return rc ? fail(rc, "ttv: launch failed") : TLIB_OK;
+        return TLIB_OK;
     }
     // n_lo == 1 with k of unit stride and n_k >= 32: every output is one
     // contiguous fiber, which the fiber kernel streams without staging
@@ -457,9 +586,11 @@ static int run_ttv(const Ten& a, const Ten& b, int mi, const Ten& c, hipStream_t
                   dname(a.dtype), (long long)P.n_lo, (long long)P.n_k, (long long)P.n_hi,
                   (long long)P.sC_lo, (long long)P.sC_hi, (long long)S, (long long)kc,
                   (long long)((P.n_hi + S - 1) / S));
-        if (g_plan_only) return TLIB_OK;
-        int rc = launch_ttv_slab(a.dtype, P, int(S), int(kc), s);
-        return rc ? fail(rc, "ttv: launch failed") : TLIB_OK;
+        L.kind = LK_TTV_SLAB;
+        L.ttv = P;
+        L.i0 = int(S);
+        L.i1 = int(kc);
+        return TLIB_OK;
     }
     // views with slabs that are not contiguous: G lanes per output fiber
     {
@@ -468,18 +599,21 @@ static int run_ttv(const Ten& a, const Ten& b, int mi, const Ten& c, hipStream_t
             const int G = P.n_k >= 256 ? 64 : P.n_k >= 64 ? 32 : P.n_k >= 16 ? 16 : 8;
             plan_note("ttv fiber dtype=%s dims=%d outputs=%lld n_k=%lld sA_k=%lld G=%d", dname(a.dtype), nd,
                       (long long)nout, (long long)P.n_k, (long long)P.sA_k, G);
-            if (g_plan_only) return TLIB_OK;
-            int rc = launch_ttv_fiber(a.dtype, P, go, G, s);
-            return rc ? fail(rc, "ttv: launch failed") : TLIB_OK;
+            L.kind = LK_TTV_FIBER;
+            L.ttv = P;
+            L.go = go;
+            L.i0 = G;
+            return TLIB_OK;
         }
     }
     GDims g;
     fill_gdims(g, d, nd, 2);
     plan_note("ttv generic dtype=%s dims=%d outputs=%lld n_k=%lld", dname(a.dtype), nd,
               (long long)g.total, (long long)P.n_k);
-    if (g_plan_only) return TLIB_OK;
-    int rc = launch_ttv_generic(a.dtype, P, g, s);
-    return rc ? fail(rc, "ttv: launch failed") : TLIB_OK;
+    L.kind = LK_TTV_GENERIC;
+    L.ttv = P;
+    L.gd[0] = g;
+    return TLIB_OK;
 }
 
 // ------------------------------------------------------------------ autotuning
@@ -516,8 +650,13 @@ static void key_ten(std::string& k, const Ten& t) {
     }
 }
 
+// *settled: the launch the call ended with is the key's lasting choice (the
+// planner's rule with autotuning off or frozen, a stored pick, or a pick just
+// tuned), so a plan cache may keep it; false when tuning was due but could
+// not run (plan-only mode, a capturing stream).
 template <class F>
-static int tuned(const std::string& key, const int* cands, int nc, hipStream_t s, F&& run) {
+static int tuned(const std::string& key, const int* cands, int nc, hipStream_t s, F&& run, bool* settled) {
+    *settled = true;
     const int mode = g_autotune.load();
     if (mode == TLIB_AUTOTUNE_OFF) return run(-1);
     int pick = PICK_NA;
@@ -534,9 +673,10 @@ static int tuned(const std::string& key, const int* cands, int nc, hipStream_t s
         }
         return run(-1);
     }
-    if (mode != TLIB_AUTOTUNE_ON || g_plan_only) return run(-1);
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return run(-1);
+    if (mode != TLIB_AUTOTUNE_ON) return run(-1);
+    *settled = false;
+    if (g_plan_only) return run(-1);
+    if (capturing(s)) return run(-1);
     static thread_local hipEvent_t e0 = nullptr, e1 = nullptr;
     if (!e0 && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) {
         e0 = e1 = nullptr;
@@ -581,15 +721,21 @@ static int tuned(const std::string& key, const int* cands, int nc, hipStream_t s
     }
     const int rc = run(bp);
     if (rc == TLIB_OK) g_plan += " autotuned(new)";
+    *settled = true;
     return rc;
 }
 
 // ------------------------------------------------------------------ GEMM planning
 
 // dm: M-group dims with strides (X, C); dn: N-group (Y, C); dk: K-group (X, Y).
+// x_is: X is operand 0 or 1 of the call.  ws_cap: scratch available when the
+// call brings a fixed buffer (SIZE_MAX: the stream's workspace).
 // tile_force >= 0 replaces the tile heuristic (autotuning candidates).
-static int run_gemm(int dtype, const void* X, const void* Y, void* C, Dim* dm, int ndm, Dim* dn,
-                    int ndn, Dim* dk, int ndk, const char* op, hipStream_t s, WsCtx& wsc, int tile_force = -1) {
+static int plan_gemm(int dtype, int x_is, const void* X, const void* Y, void* C, Dim* dm, int ndm, Dim* dn,
+                     int ndn, Dim* dk, int ndk, const char* op, size_t ws_cap, Launch& L, int tile_force = -1) {
+    L.op = op;
+    L.dtype = dtype;
+    L.xsrc = x_is;
     // Dims are stored with strides in slots 0/1 as documented above.
     int64_t M = 1, N = 1, K = 1;
     for (int i = 0; i < ndm; ++i) M *= dm[i].n;
@@ -604,6 +750,7 @@ static int run_gemm(int dtype, const void* X, const void* Y, void* C, Dim* dm, i
         return m;
     };
     if (minstride(dm, ndm, 1) < minstride(dn, ndn, 1)) {
+        L.xsrc = 1 - L.xsrc;
         std::swap(X, Y);
         std::swap(M, N);
         Dim tmp[MAXP];
@@ -700,6 +847,12 @@ static int run_gemm(int dtype, const void* X, const void* Y, void* C, Dim* dm, i
             int64_t maxk = std::max<int64_t>(1, K / (4 * bk));
             ks = int(std::min<int64_t>(std::min<int64_t>(want, maxk), 32));
         }
+        if (ws_cap != SIZE_MAX && ks > 1) {
+            // a fixed scratch buffer bounds the split: fewer slices (the same
+            // sums in another order), none when one slice does not fit
+            const size_t per = size_t(M) * size_t(N) * size_t(esize(acc_dtype(dtype)));
+            ks = int(std::max<int64_t>(1, std::min<int64_t>(ks, int64_t(ws_cap / per))));
+        }
         P.ksplit = ks;
         P.kchunk = int32_t(((K + ks - 1) / ks + bk - 1) / bk * bk);
         if (ks > 1) P.ksplit = int((K + P.kchunk - 1) / P.kchunk);
@@ -710,14 +863,13 @@ static int run_gemm(int dtype, const void* X, const void* Y, void* C, Dim* dm, i
                   "cvec=%d yvec=%d kvec=%d ksplit=%d tiles=%lld",
                   op, dname(dtype), (long long)M, (long long)N, (long long)K, ndm, ndn, ndk, ts.bm,
                   ts.bn, P.x_kfast, P.y_kfast, P.c_vec, P.y_vec, P.kvec, P.ksplit, (long long)nt);
-        wsc.need(wsb);
-        if (g_plan_only) return TLIB_OK;
-        if (P.ksplit > 1) {
-            P.part = wsc.take(wsb);
-            if (!P.part) return ws_fail(wsc, wsb, op);
-        }
-        int rc = launch_gemm(dtype, tile, P, s);
-        return rc ? fail(rc, "%s: launch failed", op) : TLIB_OK;
+        L.kind = LK_GEMM;
+        P.X = P.Y = nullptr;
+        P.C = nullptr;
+        L.gemm = P;
+        L.i0 = tile;
+        L.wsb = P.ksplit > 1 ? wsb : 0;
+        return TLIB_OK;
     }
     GDims gm, gn, gk;
     fill_gdims(gm, dm, ndm, 2);
@@ -725,9 +877,11 @@ static int run_gemm(int dtype, const void* X, const void* Y, void* C, Dim* dm, i
     fill_gdims(gk, dk, ndk, 2);
     plan_note("%s generic dtype=%s M=%lld N=%lld K=%lld dims=(%d,%d,%d)", op, dname(dtype),
               (long long)M, (long long)N, (long long)K, ndm, ndn, ndk);
-    if (g_plan_only) return TLIB_OK;
-    int rc = launch_gemm_generic(dtype, X, Y, C, gm, gn, gk, s);
-    return rc ? fail(rc, "%s: launch failed", op) : TLIB_OK;
+    L.kind = LK_GEMM_GENERIC;
+    L.gd[0] = gm;
+    L.gd[1] = gn;
+    L.gd[2] = gk;
+    return TLIB_OK;
 }
 
 static int check_ttv(const tlib_tensor* A, const tlib_tensor* b, int32_t m, const tlib_tensor* C, Ten& a,
@@ -849,9 +1003,25 @@ int tlib_ttv(const tlib_tensor* A, const tlib_tensor* b, int32_t m, const tlib_t
     Ten a, v, c;
     int rc = check_ttv(A, b, m, C, a, v, c);
     if (rc) return rc;
+    std::string key;
+    key.reserve(32 * (a.p + v.p + c.p) + 48);
+    pk(key, PCK_TTV);
+    pk(key, m);
+    pk_ten(key, a);
+    pk_ten(key, v);
+    pk_ten(key, c);
     WsCtx ws;
     ws.s = hipStream_t(stream);
-    return run_ttv(a, v, m - 1, c, hipStream_t(stream), ws);
+    auto L = pc_get(key);
+    if (L) {
+        g_plan = L->note;
+        return exec_launch(*L, a.data, v.data, c.data, ws, hipStream_t(stream));
+    }
+    Launch N;
+    if ((rc = plan_ttv(a, v, m - 1, c, N))) return rc;
+    N.note = g_plan;
+    pc_put(key, N);
+    return exec_launch(N, a.data, v.data, c.data, ws, hipStream_t(stream));
 }
 
 // One TTM launch.  pick: TTM_PICK_HEUR (planner's rule), TTM_PICK_STREAM
@@ -860,7 +1030,9 @@ int tlib_ttv(const tlib_tensor* A, const tlib_tensor* b, int32_t m, const tlib_t
 // GEMM's own tile rule).  Returns PICK_NA when the pick does not apply.
 enum { TTM_PICK_HEUR = -1, TTM_PICK_STREAM = 0, TTM_PICK_ROWS_PLAIN = 1, TTM_PICK_GEMM = 2 };
 
-static int ttm_dispatch(const Ten& a, const Ten& bm, int mi, const Ten& c, int pick, void* stream, WsCtx& wsc) {
+static int plan_ttm(const Ten& a, const Ten& bm, int mi, const Ten& c, int pick, Launch& L) {
+    L.op = "ttm";
+    L.dtype = a.dtype;
     // Short contraction: the streaming kernels (B resident in LDS, A streamed).
     {
         const int64_t Mr = bm.n[0], Kr = a.n[mi];
@@ -905,9 +1077,12 @@ static int ttm_dispatch(const Ten& a, const Ten& bm, int mi, const Ten& c, int p
                           "tiles=%lld",
                           dname(a.dtype), (long long)Mr, T.N, (long long)Kr, ndn, fm, (long long)cols, ks,
                           (long long)lds, grid, (long long)tiles);
-                if (g_plan_only) return TLIB_OK;
-                int rc2 = launch_ttm_stream(a.dtype, T, fm, ks, true, grid, hipStream_t(stream));
-                return rc2 ? fail(rc2, "ttm: launch failed") : TLIB_OK;
+                L.kind = LK_TTM_STREAM;
+                L.tstr = T;
+                L.i0 = fm;
+                L.i1 = ks;
+                L.i2 = grid;
+                return TLIB_OK;
             }
         } else if (!trans && pick <= 1 && Mr <= 256 && ndn >= 1 && ndn <= GMAXD + 1 && ncols < (int64_t(1) << 31)) {
             // C strided along j: runs along C's innermost column dim
@@ -973,9 +1148,12 @@ static int ttm_dispatch(const Ten& a, const Ten& bm, int mi, const Ten& c, int p
                                                  : mode == TTM_ROWS_ALIGNED ? "aligned" : "plain",
                           (long long)Mr, (long long)Kr, (long long)n_lo, (long long)(ncols / n_lo), (long long)tc, ks,
                           (long long)lds, nrg, mr, grid);
-                if (g_plan_only) return TLIB_OK;
-                int rc2 = launch_ttm_rows(a.dtype, R, mode, ks, grid, hipStream_t(stream));
-                return rc2 ? fail(rc2, "ttm: launch failed") : TLIB_OK;
+                L.kind = LK_TTM_ROWS;
+                L.trow = R;
+                L.i0 = mode;
+                L.i1 = ks;
+                L.i2 = grid;
+                return TLIB_OK;
             }
         }
     }
@@ -988,13 +1166,23 @@ static int ttm_dispatch(const Ten& a, const Ten& bm, int mi, const Ten& c, int p
         if (r != mi) dn[ndn++] = {a.n[r], {a.w[r], c.w[r], 0}};
     Dim dk[1] = {{a.n[mi], {bm.w[1], a.w[mi], 0}}};
     const int tile = pick >= TTM_PICK_GEMM ? pick - TTM_PICK_GEMM : -1;
-    return run_gemm(a.dtype, bm.data, a.data, c.data, dm, 1, dn, ndn, dk, 1, "ttm", hipStream_t(stream), wsc,
-                    tile < GT_COUNT ? tile : -1);
+    return plan_gemm(a.dtype, 1, bm.data, a.data, c.data, dm, 1, dn, ndn, dk, 1, "ttm", SIZE_MAX, L,
+                     tile < GT_COUNT ? tile : -1);
+}
+
+// Plan and launch one TTM (no plan cache): the pieces of a ttm2 chain.
+static int ttm_dispatch(const Ten& a, const Ten& bm, int mi, const Ten& c, int pick, void* stream, WsCtx& wsc) {
+    Launch L;
+    const int rc = plan_ttm(a, bm, mi, c, pick, L);
+    if (rc != TLIB_OK) return rc;
+    return exec_launch(L, a.data, bm.data, c.data, wsc, hipStream_t(stream));
 }
 
 int tlib_set_autotune(int mode) {
     if (mode != TLIB_AUTOTUNE_OFF && mode != TLIB_AUTOTUNE_ON && mode != TLIB_AUTOTUNE_FROZEN) return -1;
-    return g_autotune.exchange(mode);
+    const int prev = g_autotune.exchange(mode);
+    if (prev != mode) pc_clear();
+    return prev;
 }
 
 int64_t tlib_autotune_entries(void) {
@@ -1003,8 +1191,11 @@ int64_t tlib_autotune_entries(void) {
 }
 
 void tlib_autotune_clear(void) {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune.clear();
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune.clear();
+    }
+    pc_clear();
 }
 
 int tlib_autotune_save(const char* path) {
@@ -1041,6 +1232,7 @@ int tlib_autotune_load(const char* path) {
         g_tune[std::string(line + used)] = pick;
     }
     fclose(f);
+    pc_clear();
     return rc;
 }
 
@@ -1051,6 +1243,21 @@ int tlib_ttm(const tlib_tensor* A, const tlib_tensor* B, int32_t m, const tlib_t
     int rc = check_ttm(A, B, m, C, a, bm, c);
     if (rc) return rc;
     const int mi = m - 1;
+    const hipStream_t s = hipStream_t(stream);
+    std::string pkey;
+    pkey.reserve(32 * (a.p + bm.p + c.p) + 48);
+    pk(pkey, PCK_TTM);
+    pk(pkey, m);
+    pk_ten(pkey, a);
+    pk_ten(pkey, bm);
+    pk_ten(pkey, c);
+    WsCtx ws;
+    ws.s = s;
+    auto L = pc_get(pkey);
+    if (L) {
+        g_plan = L->note;
+        return exec_launch(*L, a.data, bm.data, c.data, ws, s);
+    }
     static const int cands[] = {TTM_PICK_STREAM,          TTM_PICK_ROWS_PLAIN,        TTM_PICK_GEMM + GT_COUNT,
                                 TTM_PICK_GEMM + GT_128x64, TTM_PICK_GEMM + GT_128x128, TTM_PICK_GEMM + GT_64x128,
                                 TTM_PICK_GEMM + GT_256x64};
@@ -1059,12 +1266,22 @@ int tlib_ttm(const tlib_tensor* A, const tlib_tensor* B, int32_t m, const tlib_t
     key_ten(key, a);
     key_ten(key, bm);
     key_ten(key, c);
-    WsCtx ws;
-    ws.s = hipStream_t(stream);
-    return tuned(key, cands, int(sizeof(cands) / sizeof(cands[0])), hipStream_t(stream), [&](int pick) {
+    Launch last;
+    bool settled = false;
+    rc = tuned(key, cands, int(sizeof(cands) / sizeof(cands[0])), s, [&](int pick) {
+        Launch N;
+        int r = plan_ttm(a, bm, mi, c, pick, N);
+        if (r != TLIB_OK) return r;
         ws.used = 0;
-        return ttm_dispatch(a, bm, mi, c, pick, stream, ws);
-    });
+        r = exec_launch(N, a.data, bm.data, c.data, ws, s);
+        if (r == TLIB_OK) last = std::move(N);
+        return r;
+    }, &settled);
+    if (rc == TLIB_OK && settled && last.kind != LK_NONE) {
+        last.note = g_plan;
+        pc_put(pkey, last);
+    }
+    return rc;
 }
 
 // Two mode products C = (A x_a Ua) x_b Ub in one pass (Sec. 5.2 Eq. ttm
@@ -1199,10 +1416,8 @@ int tlib_ttm2(const tlib_tensor* A, const tlib_tensor* Ua, int32_t ma, const tli
     return ttm_dispatch(t, ub, ib, c, TTM_PICK_HEUR, stream, ws);
 }
 
-int tlib_ttt(const tlib_tensor* A, const tlib_tensor* B, int32_t q, const int32_t* phi,
-             const int32_t* psi, const tlib_tensor* C, void* stream) {
-    begin_call();
-    Ten a, b, c;
+static int check_ttt(const tlib_tensor* A, const tlib_tensor* B, int32_t q, const int32_t* phi, const int32_t* psi,
+                     const tlib_tensor* C, Ten& a, Ten& b, Ten& c) {
     int rc;
     if ((rc = normalize(A, a, "A")) || (rc = normalize(B, b, "B")) || (rc = normalize(C, c, "C")))
         return rc;
@@ -1225,19 +1440,35 @@ int tlib_ttt(const tlib_tensor* A, const tlib_tensor* B, int32_t q, const int32_
     if (c.dtype != acc_dtype(a.dtype)) return fail(TLIB_EDTYPE, "ttt: C must be %s", dname(acc_dtype(a.dtype)));
     if ((rc = check_output(c, "C"))) return rc;
     if (overlaps(c, a) || overlaps(c, b)) return fail(TLIB_EALIAS, "ttt: C overlaps an input");
-    // GEMM roles: X = A (M = free A modes), Y = B (N = free B modes), K = pairs.
-    WsCtx ws;
-    ws.s = hipStream_t(stream);
-    auto run = [&](int tile) {
-        ws.used = 0;
-        Dim dm[MAXP], dn[MAXP], dk[MAXP];
-        for (int k = 0; k < r; ++k) dm[k] = {a.n[phi[k] - 1], {a.w[phi[k] - 1], c.w[k], 0}};
-        for (int k = 0; k < s; ++k) dn[k] = {b.n[psi[k] - 1], {b.w[psi[k] - 1], c.w[r + k], 0}};
-        for (int k = 0; k < q; ++k)
-            dk[k] = {a.n[phi[r + k] - 1], {a.w[phi[r + k] - 1], b.w[psi[s + k] - 1], 0}};
-        return run_gemm(a.dtype, a.data, b.data, c.data, dm, r, dn, s, dk, q, "ttt", hipStream_t(stream), ws, tile);
-    };
-    static const int cands[] = {GT_16x256, GT_64x128, GT_128x128, GT_256x64, GT_64x64, GT_128x64, GT_256x32};
+    return TLIB_OK;
+}
+
+// GEMM roles: X = A (M = free A modes), Y = B (N = free B modes), K = pairs.
+static int plan_ttt(const Ten& a, const Ten& b, int q, const int32_t* phi, const int32_t* psi, const Ten& c,
+                    size_t ws_cap, Launch& L, int tile) {
+    const int r = a.p - q, s = b.p - q;
+    Dim dm[MAXP], dn[MAXP], dk[MAXP];
+    for (int k = 0; k < r; ++k) dm[k] = {a.n[phi[k] - 1], {a.w[phi[k] - 1], c.w[k], 0}};
+    for (int k = 0; k < s; ++k) dn[k] = {b.n[psi[k] - 1], {b.w[psi[k] - 1], c.w[r + k], 0}};
+    for (int k = 0; k < q; ++k) dk[k] = {a.n[phi[r + k] - 1], {a.w[phi[r + k] - 1], b.w[psi[s + k] - 1], 0}};
+    return plan_gemm(a.dtype, 0, a.data, b.data, c.data, dm, r, dn, s, dk, q, "ttt", ws_cap, L, tile);
+}
+
+static std::string ttt_pkey(int kind, const Ten& a, const Ten& b, const Ten& c, int q, const int32_t* phi,
+                            const int32_t* psi) {
+    std::string key;
+    key.reserve(32 * (a.p + b.p + c.p) + 64);
+    pk(key, kind);
+    pk(key, q);
+    for (int k = 0; k < a.p; ++k) pk(key, phi[k]);
+    for (int k = 0; k < b.p; ++k) pk(key, psi[k]);
+    pk_ten(key, a);
+    pk_ten(key, b);
+    pk_ten(key, c);
+    return key;
+}
+
+static std::string ttt_key(const Ten& a, const Ten& b, const Ten& c, int q, const int32_t* phi, const int32_t* psi) {
     std::string key = "ttt";
     key_int(key, q);
     for (int k = 0; k < a.p; ++k) key_int(key, phi[k]);
@@ -1245,7 +1476,42 @@ int tlib_ttt(const tlib_tensor* A, const tlib_tensor* B, int32_t q, const int32_
     key_ten(key, a);
     key_ten(key, b);
     key_ten(key, c);
-    return tuned(key, cands, int(sizeof(cands) / sizeof(cands[0])), hipStream_t(stream), run);
+    return key;
+}
+
+int tlib_ttt(const tlib_tensor* A, const tlib_tensor* B, int32_t q, const int32_t* phi,
+             const int32_t* psi, const tlib_tensor* C, void* stream) {
+    begin_call();
+    Ten a, b, c;
+    int rc = check_ttt(A, B, q, phi, psi, C, a, b, c);
+    if (rc) return rc;
+    const hipStream_t st = hipStream_t(stream);
+    const std::string pkey = ttt_pkey(PCK_TTT, a, b, c, q, phi, psi);
+    WsCtx ws;
+    ws.s = st;
+    auto L = pc_get(pkey);
+    if (L) {
+        g_plan = L->note;
+        return exec_launch(*L, a.data, b.data, c.data, ws, st);
+    }
+    Launch last;
+    bool settled = false;
+    auto run = [&](int tile) {
+        Launch N;
+        int r = plan_ttt(a, b, q, phi, psi, c, SIZE_MAX, N, tile);
+        if (r != TLIB_OK) return r;
+        ws.used = 0;
+        r = exec_launch(N, a.data, b.data, c.data, ws, st);
+        if (r == TLIB_OK) last = std::move(N);
+        return r;
+    };
+    static const int cands[] = {GT_16x256, GT_64x128, GT_128x128, GT_256x64, GT_64x64, GT_128x64, GT_256x32};
+    rc = tuned(ttt_key(a, b, c, q, phi, psi), cands, int(sizeof(cands) / sizeof(cands[0])), st, run, &settled);
+    if (rc == TLIB_OK && settled && last.kind != LK_NONE) {
+        last.note = g_plan;
+        pc_put(pkey, last);
+    }
+    return rc;
 }
 
 static int run_dot(const Ten& a, const Ten* b, double* out, bool sq, hipStream_t s, const char* op) {
@@ -1685,6 +1951,15 @@ int tlib_workspace_release(void* stream) {
     g_ws.erase(it);
     return TLIB_OK;
 }
+
+void tlib_plan_cache_stats(int64_t* entries, int64_t* hits, int64_t* misses) {
+    std::lock_guard<std::mutex> lk(g_pc_mu);
+    if (entries) *entries = int64_t(g_pc.size());
+    if (hits) *hits = g_pc_hits.load();
+    if (misses) *misses = g_pc_misses.load();
+}
+
+void tlib_plan_cache_clear(void) { pc_clear(); }
 
 const char* tlib_last_error(void) { return g_err.c_str(); }
 

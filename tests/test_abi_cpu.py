@@ -392,3 +392,65 @@ def test_config3_ttt_plans_split_k():
         rc = L.tlib_ttt(ctypes.byref(A), ctypes.byref(B), 2, _lib.i32_array((1, 2, 3, 4)),
                         _lib.i32_array((3, 1, 2)), ctypes.byref(C), None)
         assert rc == 0 and int(_plan().split("ksplit=")[1].split()[0]) > 1, _plan()
+
+
+def _cache_stats():
+    e, h, m = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _lib.lib().tlib_plan_cache_stats(ctypes.byref(e), ctypes.byref(h), ctypes.byref(m))
+    return e.value, h.value, m.value
+
+
+def test_plan_cache_reuses_plans():
+    """A repeated call shape takes its plan from the cache (the plan text is
+    the same and the hit count grows); another stride, mode or address
+    alignment is a new shape (Sec. 3.1 Eq. stride.tuple.permutation: the
+    strides decide the plan)."""
+    L = _lib.lib()
+    L.tlib_plan_cache_clear()
+    phi, psi = _lib.i32_array((1, 2, 3, 4)), _lib.i32_array((3, 1, 2))
+    calls = []
+    for dt in (_lib.F64, _lib.F32):
+        for lay in (None, (3, 2, 1), (2, 3, 1)):
+            A = _d((40, 33, 29), dt, layout=lay)
+            for m in (1, 2, 3):
+                nb = [40, 33, 29]
+                b = _d((nb[m - 1],), dt, ptr=FAKE * 2)
+                cv = [n for i, n in enumerate(nb) if i != m - 1]
+                C = _d(tuple(cv), _lib.F64 if dt == _lib.F64 else _lib.F32, ptr=FAKE * 3)
+                calls.append(lambda A=A, b=b, m=m, C=C: _ttv(A, b, m, C))
+                B = _d((17, nb[m - 1]), dt, ptr=FAKE * 2)
+                cm = list(nb)
+                cm[m - 1] = 17
+                Cm = _d(tuple(cm), _lib.F64 if dt == _lib.F64 else _lib.F32, ptr=FAKE * 3)
+                calls.append(lambda A=A, B=B, m=m, Cm=Cm: _ttm(A, B, m, Cm))
+        At = _d((12, 10, 8, 6), dt, layout=(3, 1, 4, 2))
+        Bt = _d((8, 6, 14), dt, ptr=FAKE * 2)
+        Ct = _d((12, 10, 14), _lib.F64 if dt == _lib.F64 else _lib.F32, ptr=FAKE * 3)
+        calls.append(lambda At=At, Bt=Bt, Ct=Ct: L.tlib_ttt(ctypes.byref(At), ctypes.byref(Bt), 2, phi, psi,
+                                                           ctypes.byref(Ct), None))
+    with Plan():
+        first = []
+        for f in calls:
+            assert f() == 0
+            first.append(_plan())
+        e0, h0, m0 = _cache_stats()
+        assert e0 == len(calls)
+        for f, p0 in zip(calls, first):
+            assert f() == 0
+            assert _plan() == p0
+        e1, h1, m1 = _cache_stats()
+        assert (e1, h1 - h0, m1 - m0) == (e0, len(calls), 0)
+        # the same TTV at an address 8 bytes off is another shape: FP64 lanes
+        # along lo may no longer load 16-byte vectors
+        A = _d((256, 4, 3000), _lib.F64, ptr=FAKE)
+        A8 = _d((256, 4, 3000), _lib.F64, ptr=FAKE + 8)
+        b = _d((4,), _lib.F64, ptr=FAKE * 2)
+        C = _d((256, 3000), _lib.F64, ptr=FAKE * 3)
+        assert _ttv(A, b, 2, C) == 0
+        p_al = _plan()
+        assert _ttv(A8, b, 2, C) == 0
+        p_un = _plan()
+        assert "vec=2" in p_al and "vec=1" in p_un, (p_al, p_un)
+        assert _cache_stats()[0] == e0 + 2
+    L.tlib_plan_cache_clear()
+    assert _cache_stats()[0] == 0
