@@ -92,6 +92,7 @@ def build_cases(T, torch, dev, quick=False):
         st = T.strides(shape, layout)
         return torch.as_strided(outbuf[d], shape, st)
 
+    rot = 0  # running call index: consecutive calls never read the same copy of a tensor
     for d in dtypes:
         s = ESZ[d]
         for p in ps:
@@ -110,7 +111,8 @@ def build_cases(T, torch, dev, quick=False):
                 keep.append(b)
                 keep.extend(Bm.values())
                 for q in range(1, p + 1):
-                    A = As[q % 2]
+                    A = As[rot % 2]
+                    rot += 1
                     cshape = shape[: q - 1] + shape[q:]
                     clay = [r if r < q else r - 1 for r in lay if r != q]
                     C = out_view(d, cshape, clay)
@@ -119,7 +121,8 @@ def build_cases(T, torch, dev, quick=False):
                     cases[-1].planfn = _plan_later(T, T.ttv, A, b, q, out=C)
                 for q in range(1, p + 1):
                     for m in TTM_M:
-                        A = As[(q + m) % 2]
+                        A = As[rot % 2]
+                        rot += 1
                         cshape = shape[: q - 1] + (m,) + shape[q:]
                         C = out_view(d, cshape, lay)
                         nb = s * (N + m * n) + s * (N // n * m)
@@ -547,10 +550,43 @@ def run_step(cases, torch, ev):
             ev[i][1].record()
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline_both(budget_s=15.0, budget_1t_s=12.0):
+    """The oracle with the host's OpenMP threads (this process), then
+    single-threaded in a child process (OMP_NUM_THREADS=1), on the same
+    sample plan."""
+    import subprocess
+
+    res = cpu_baseline(budget_s)
+    res["cpu_model"] = cpu_model()
+    res["nproc"] = os.cpu_count()
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only",
+                            "--cpu-budget", str(budget_1t_s)], env=env, capture_output=True, text=True,
+                           timeout=10 * budget_1t_s + 120)
+        one = json.loads(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 else None
+    except (subprocess.TimeoutExpired, ValueError, IndexError):
+        one = None
+    res["single_thread"] = one
+    return res
+
+
 def cpu_baseline(budget_s=15.0):
     """The FP64 oracle on a bounded sample of the same sweep: TTV and TTM
-    (m=16) in mode 2 of the first-order p=3 (406^3) and p=5 (36^5) tensors,
-    then further modes until about `budget_s` seconds of CPU work."""
+    (m = 16, 64) in modes 2, 1, p, 3, ... of the first-order p = 3, 5, 7, 4, 6
+    tensors (406^3, 36^5, 13^7, 90^4, 20^6), in that order, until about
+    `budget_s` seconds of CPU work (each case run once)."""
     import numpy as np
 
     import oracle
@@ -615,10 +651,15 @@ def main():
                          "mixed request stream (latency / req/s); drivers: Tucker, multi-mode TTV, HOPM; "
                          "views: operations on strided views against dense tensors")
     ap.add_argument("--requests", type=int, default=10000, help="serve: stream length")
+    ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help=argparse.SUPPRESS)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (3 times), the reference for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale")
     args = ap.parse_args()
+    if args.cpu_baseline_only:
+        print(json.dumps(cpu_baseline(args.cpu_budget)))
+        return
     if args.calibrate_copy:
         import torch
 
@@ -759,7 +800,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         del keep, outbuf
-        cpu = cpu_baseline()
+        cpu = cpu_baseline_both()
 
     out = {
         "metric": METRIC,
