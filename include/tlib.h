@@ -123,6 +123,24 @@ int tlib_ttt(const tlib_tensor* A, const tlib_tensor* B, int32_t q,
              const int32_t* phi, const int32_t* psi,
              const tlib_tensor* C, void* stream);
 
+/* tlib_ttt for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same operation, arguments and errors as tlib_ttt, but no workspace.  Its
+ * split-K partials live in a static device array of
+ * TLIB_NOALLOC_SCRATCH_BYTES per GPU, part of the library's code object and
+ * held until the process ends; the split is bounded by that size (a product
+ * whose single slice would not fit runs unsplit, so no size is refused; a
+ * plan that needed more would return TLIB_ENOMEM before launching).  The tile
+ * is the planner's rule (no autotuning).  The call allocates nothing and never
+ * synchronises.  Every call on one GPU shares that GPU's array, which keeps
+ * the last call's partials: calls that may overlap on one GPU (different
+ * streams, or graphs replayed concurrently) race on it and must be ordered by
+ * the caller.  Results equal tlib_ttt's within the summation-order rounding. */
+#define TLIB_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+int tlib_ttt_noalloc(const tlib_tensor* A, const tlib_tensor* B, int32_t q,
+                     const int32_t* phi, const int32_t* psi,
+                     const tlib_tensor* C, void* stream);
+
 /* Inner product <A, B> = sum_i A(i) B(i) (Sec. 5.2 Table 3) over equal shapes
  * with independent layouts.  Accumulates in FP64 in a fixed order that only
  * depends on the shapes and strides; writes one double to out_dev (device). */

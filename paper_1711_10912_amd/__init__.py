@@ -19,7 +19,7 @@ from . import _lib
 from ._lib import TlibError
 
 __all__ = [
-    "ttv", "ttm", "ttt", "inner", "norm", "add", "scale", "transpose", "times_tensor",
+    "ttv", "ttm", "ttt", "ttt_noalloc", "inner", "norm", "add", "scale", "transpose", "times_tensor",
     "times_vectors", "strides", "layout_of", "empty", "TlibError", "plan", "hopm", "tucker",
     "set_autotune", "autotune_entries", "autotune_clear", "autotune_save", "autotune_load",
     "workspace_reserve", "workspace_size", "workspace_release",
@@ -155,6 +155,16 @@ def ttt(A, B, q: int, phi: Sequence[int], psi: Sequence[int], out=None, layout=N
     _lib.check(_lib.lib().tlib_ttt(ctypes.byref(_desc(A)), ctypes.byref(_desc(B)), int(q),
                                    _lib.i32_array(phi), _lib.i32_array(psi), ctypes.byref(_desc(out)),
                                    _stream(A)))
+    return out
+
+
+def ttt_noalloc(A, B, q: int, phi: Sequence[int], psi: Sequence[int], out):
+    """tlib_ttt_noalloc: the same contraction with its split-K scratch in the
+    library's static device array (the library allocates nothing; `out` is
+    required, so this call allocates nothing either)."""
+    _lib.check(_lib.lib().tlib_ttt_noalloc(ctypes.byref(_desc(A)), ctypes.byref(_desc(B)), int(q),
+                                           _lib.i32_array(phi), _lib.i32_array(psi), ctypes.byref(_desc(out)),
+                                           _stream(A)))
     return out
 
 

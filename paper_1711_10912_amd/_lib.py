@@ -16,7 +16,7 @@ OK, EINVAL, ESHAPE, EMODE, EDTYPE, EALIAS, ESTRIDE, ENOMEM, EHIP = range(9)
 MAX_ORDER = 16
 
 EXPORTS = (
-    "tlib_ttv", "tlib_ttm", "tlib_ttm2", "tlib_ttt", "tlib_inner", "tlib_norm", "tlib_add", "tlib_scale",
+    "tlib_ttv", "tlib_ttm", "tlib_ttm2", "tlib_ttt", "tlib_ttt_noalloc", "tlib_inner", "tlib_norm", "tlib_add", "tlib_scale",
     "tlib_transpose", "tlib_times_vectors", "tlib_batch_table_bytes", "tlib_batch_plan", "tlib_batch_run",
     "tlib_request_check", "tlib_server_create", "tlib_server_submit", "tlib_server_drain", "tlib_server_stats",
     "tlib_server_result", "tlib_server_reset_stats", "tlib_server_destroy",
@@ -79,6 +79,7 @@ def lib():
         L.tlib_ttm.argtypes = [P, P, ctypes.c_int32, P, vp]
         L.tlib_ttm2.argtypes = [P, P, ctypes.c_int32, P, ctypes.c_int32, P, vp]
         L.tlib_ttt.argtypes = [P, P, ctypes.c_int32, i32p, i32p, P, vp]
+        L.tlib_ttt_noalloc.argtypes = [P, P, ctypes.c_int32, i32p, i32p, P, vp]
         L.tlib_inner.argtypes = [P, P, vp, vp]
         L.tlib_norm.argtypes = [P, vp, vp]
         L.tlib_add.argtypes = [ctypes.c_double, P, ctypes.c_double, P, P, vp]
@@ -120,7 +121,7 @@ def lib():
         L.tlib_server_reset_stats.restype = None
         L.tlib_server_destroy.argtypes = [vp]
         L.tlib_server_destroy.restype = None
-        for f in ("tlib_ttv", "tlib_ttm", "tlib_ttm2", "tlib_ttt", "tlib_inner", "tlib_norm", "tlib_add",
+        for f in ("tlib_ttv", "tlib_ttm", "tlib_ttm2", "tlib_ttt", "tlib_ttt_noalloc", "tlib_inner", "tlib_norm", "tlib_add",
                   "tlib_scale", "tlib_transpose", "tlib_times_vectors", "tlib_strides_from_layout"):
             getattr(L, f).restype = ctypes.c_int
         L.tlib_last_error.restype = ctypes.c_char_p

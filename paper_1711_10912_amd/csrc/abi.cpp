@@ -391,7 +391,7 @@ std::mutex g_pc_mu;
 std::unordered_map<std::string, std::shared_ptr<const Launch>> g_pc;
 std::atomic<int64_t> g_pc_hits{0}, g_pc_misses{0};
 constexpr size_t PC_MAX = 8192;
-enum { PCK_TTV = 1, PCK_TTM = 2, PCK_TTT = 3 };
+enum { PCK_TTV = 1, PCK_TTM = 2, PCK_TTT = 3, PCK_TTT_NOALLOC = 4 };
 }  // namespace
 
 static void pk(std::string& k, int64_t v) { k.append(reinterpret_cast<const char*>(&v), sizeof(v)); }
@@ -995,6 +995,42 @@ static void begin_call() {
 
 using namespace tlib;
 
+// ------------------------------------------------------------------ static scratch (no-allocation TTT)
+//
+// Split-K partials of tlib_ttt_noalloc live in this file-scope device array:
+// one copy per GPU, loaded with the library's code object and held until the
+// process ends.  On the host the array's name is only a stand-in, never a
+// device address: host code uses the address that hipGetSymbolAddress
+// returns, looked up once per device (with that device current) on the first
+// call there and kept in g_scratch_dev.
+static __device__ __align__(256) unsigned char scratch[TLIB_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[SCRATCH_MAX_DEVICES] = {};
+}  // namespace
+
+static int scratch_address(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(TLIB_EHIP, "ttt_noalloc: no current device");
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES)
+        return fail(TLIB_EINVAL, "ttt_noalloc: device %d beyond the %d supported", dev, SCRATCH_MAX_DEVICES);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(TLIB_EHIP, "ttt_noalloc: hipGetSymbolAddress of the scratch array failed (%s)",
+                        hipGetErrorString(e));
+        }
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return TLIB_OK;
+}
+
 extern "C" {
 
 int tlib_ttv(const tlib_tensor* A, const tlib_tensor* b, int32_t m, const tlib_tensor* C,
@@ -1510,6 +1546,43 @@ int tlib_ttt(const tlib_tensor* A, const tlib_tensor* B, int32_t q, const int32_
     if (rc == TLIB_OK && settled && last.kind != LK_NONE) {
         last.note = g_plan;
         pc_put(pkey, last);
+    }
+    return rc;
+}
+
+// TTT whose scratch is the static array above: the split-K slices are bounded
+// by its size (fewer slices, the same sums in another order; none when one
+// slice does not fit), the tile is the planner's rule (no autotuning, which
+// would synchronise), and nothing is allocated.  Partials are written in full
+// by every call before they are summed, so the array needs no clearing.
+int tlib_ttt_noalloc(const tlib_tensor* A, const tlib_tensor* B, int32_t q, const int32_t* phi,
+                     const int32_t* psi, const tlib_tensor* C, void* stream) {
+    begin_call();
+    Ten a, b, c;
+    int rc = check_ttt(A, B, q, phi, psi, C, a, b, c);
+    if (rc) return rc;
+    const hipStream_t st = hipStream_t(stream);
+    WsCtx ws;
+    ws.s = st;
+    ws.fixed = true;
+    ws.size = TLIB_NOALLOC_SCRATCH_BYTES;
+    if (!g_plan_only) {
+        void* p = nullptr;
+        if ((rc = scratch_address(&p))) return rc;
+        ws.base = static_cast<char*>(p);
+    }
+    const std::string pkey = ttt_pkey(PCK_TTT_NOALLOC, a, b, c, q, phi, psi);
+    if (auto L = pc_get(pkey)) {
+        g_plan = L->note;
+        return exec_launch(*L, a.data, b.data, c.data, ws, st);
+    }
+    Launch N;
+    rc = plan_ttt(a, b, q, phi, psi, c, TLIB_NOALLOC_SCRATCH_BYTES, N, -1);
+    if (rc) return rc;
+    rc = exec_launch(N, a.data, b.data, c.data, ws, st);
+    if (rc == TLIB_OK) {
+        N.note = g_plan;
+        pc_put(pkey, N);
     }
     return rc;
 }

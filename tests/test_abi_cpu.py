@@ -159,6 +159,49 @@ def test_first_order_ttt_collapses_to_plain_gemm():
         assert rc == 0 and "dims=(1,1,1)" in _plan()
 
 
+def _ksplit(plan):
+    return int(plan.split("ksplit=")[1].split()[0])
+
+
+def test_ttt_noalloc_bounds_its_split_by_the_static_scratch():
+    """tlib_ttt_noalloc plans the same contraction as tlib_ttt (Sec. 5.2
+    Eq. ttt) with its split-K slices bounded by the static scratch size."""
+    L = _lib.lib()
+    cap = 16 << 20
+    with Plan():
+        for (na, nb, nc, dt, es) in (((96, 80, 64, 48), (64, 48, 120), (96, 80, 120), _lib.F32, 4),  # 3.7 MB a slice
+                                     ((8, 4, 4096), (4, 4096, 8), (8, 8), _lib.F32, 4),  # tiny M N, deep K
+                                     ((1500, 512), (512, 1500), (1500, 1500), _lib.F64, 8)):  # a slice > cap
+            Ad = _d(na, dt)
+            Bd = _d(nb, dt, ptr=FAKE * 2)
+            Cd = _d(nc, dt, ptr=FAKE * 3)
+            q = (len(na) + len(nb) - len(nc)) // 2
+            phi = _lib.i32_array(tuple(range(1, len(na) + 1)))
+            psi = _lib.i32_array(tuple(range(q + 1, len(nb) + 1)) + tuple(range(1, q + 1)))
+            assert L.tlib_ttt(ctypes.byref(Ad), ctypes.byref(Bd), q, phi, psi, ctypes.byref(Cd), None) == 0
+            ref = _plan()
+            assert L.tlib_ttt_noalloc(ctypes.byref(Ad), ctypes.byref(Bd), q, phi, psi, ctypes.byref(Cd), None) == 0
+            got = _plan()
+            mn = 1
+            for e in nc:
+                mn *= e
+            assert _ksplit(got) <= max(1, cap // (es * mn)), got
+            if es * mn > cap:
+                assert _ksplit(ref) > 1 and _ksplit(got) == 1
+            assert _ksplit(got) <= _ksplit(ref)
+            # everything but the split is the same plan
+            strip = lambda p: p.split(" ksplit=")[0]
+            assert strip(got) == strip(ref)
+        # the same errors as tlib_ttt
+        Ad = _d((3, 4, 2, 6))
+        Cd = _d((2, 3, 4), ptr=FAKE * 2)
+        Ed = _d((3, 6, 3), ptr=FAKE * 3)
+        assert L.tlib_ttt_noalloc(ctypes.byref(Ad), ctypes.byref(Cd), 2, _lib.i32_array((1, 4, 3, 2)),
+                                  _lib.i32_array((2, 3, 1)), ctypes.byref(Ed), None) == _lib.ESHAPE
+        assert L.tlib_ttt_noalloc(ctypes.byref(Ad), ctypes.byref(Cd), 2, _lib.i32_array((1, 1, 2, 3)),
+                                  _lib.i32_array((2, 3, 1)), ctypes.byref(Ed), None) == _lib.EMODE
+
+
 def test_error_codes():
     with Plan():
         A = _d((4, 5, 6))
