@@ -10,7 +10,13 @@ layout, FP64 and FP32:
     every sweep tensor,
 plus the general TTT case: A (96,80,64,48) in first-order, last-order and
 (3,1,4,2) layout times B (64,48,120), contracting A{3,4} with B{1,2}, in FP32,
-BF16 and FP16 (FP32 accumulation).
+BF16 and FP16 (FP32 accumulation), and the outer product (TTT with no
+contracted pair) of A (512,128) and B (64,40) in FP64 and FP32.
+
+After the timed steps the served mixed request stream is measured (closed
+loop, open loop at 0.5 / 0.8 / 0.95 of capacity, the plain per-call FP64 path
+on the same requests) and every served result is checked against the FP64
+oracle; then the oracle itself is timed on a sample of the sweep.
 
 Inputs are resident in HBM before timing starts; each call alternates between
 two copies of its input tensor (several for the TTT operands) so that the
@@ -143,6 +149,19 @@ def build_cases(T, torch, dev, quick=False):
                 cases[-1].planfn = _plan_later(T, T.add, 1.0, As[0], 1.0, As[1], out=C)
                 keep.append(res)
 
+    # outer product (q = 0): A (512,128) x B (64,40) -> C (512,128,64,40), a
+    # write stream of 167.8M outputs
+    for d in dtypes:
+        oa, ob = (512, 128), (64, 40)
+        A = torch.rand(oa, generator=gen, device=dev, dtype=tdt[d]).mul_(2).sub_(1)
+        B = torch.rand(ob, generator=gen, device=dev, dtype=tdt[d]).mul_(2).sub_(1)
+        keep.extend((A, B))
+        C = out_view(d, oa + ob, None)
+        Mo, No = 512 * 128, 64 * 40
+        cases.append(Case("outer (512,128)x(64,40) %s" % d, "outer", ESZ[d] * (Mo + No + Mo * No), Mo * No, d,
+                          (lambda A=A, B=B, C=C: T.ttt(A, B, 0, (1, 2), (1, 2), out=C))))
+        cases[-1].planfn = _plan_later(T, T.ttt, A, B, 0, (1, 2), (1, 2), out=C)
+
     # TTT: A (96,80,64,48) x B (64,48,120), A{3,4} <-> B{1,2}
     na, nbs = (96, 80, 64, 48), (64, 48, 120)
     phi, psi = (1, 2, 3, 4), (3, 1, 2)
@@ -249,22 +268,31 @@ def served_workload(n_req, n_tensors, n_mats, cap, seed_case=0, device="cuda:0",
     return reqs, operands
 
 
-def serve_bench(args):
-    """Served mixed stream: closed-loop capacity, open-loop Poisson arrivals at
-    0.8 x capacity (p50/p99 latency), and the plain per-call synchronous FP64
-    path on the same requests for comparison."""
+SERVE_RATES = (0.5, 0.8, 0.95)  # open-loop arrival rates as fractions of the closed-loop capacity
+SERVE_TIE_EVERY = 50  # in the headline open-loop run every 50th result is kept (caller-owned output)
+CHECK_MACS = 1 << 19  # oracle multiply-adds per served result in the offline check
+# kernel choices for the served stream's shape classes, tuned on MI355X
+SERVED_TABLE = os.path.join(HERE, "paper_1711_10912_amd", "tuning", "mi355x_served.txt")
+
+
+def served_measure(n_req, slots=4, budget=64 << 30, check=True, log=None, table=SERVED_TABLE, tune_save=""):
+    """The served mixed stream on the native server: closed-loop capacity,
+    open-loop Poisson arrivals at 0.5 / 0.8 / 0.95 x that capacity (p50/p99
+    latency, arrival to completion), the plain per-call synchronous FP64 path
+    on the same requests, and (after all timing) every served result checked
+    against the FP64 oracle."""
     import numpy as np
     import torch
 
     import paper_1711_10912_amd as T
     from paper_1711_10912_amd.serve import Server
 
+    log = log or (lambda *a: print(*a, file=sys.stderr, flush=True))
     t0 = time.perf_counter()
-    reqs, operands = served_workload(args.requests, 1024, 256, 1 << 24)
-    print("serve: workload ready (%d requests, %.1f s)" % (len(reqs), time.perf_counter() - t0),
-          file=sys.stderr, flush=True)
+    reqs, operands = served_workload(n_req, 1024, 256, 1 << 24)
+    log("serve: workload ready (%d requests, %.1f s)" % (len(reqs), time.perf_counter() - t0))
 
-    def run(srv, subset, rate=None):
+    def run(srv, subset, rate=None, outs=None):
         srv.reset_stats()
         t_start = time.perf_counter()
         arr = 0.0
@@ -275,22 +303,51 @@ def serve_bench(args):
                 arr += g.exponential(1.0 / rate)
                 while time.perf_counter() - t_start < arr:
                     pass
-            srv.submit(r.op, a, b, mode=r.mode, q=r.q, phi=r.phi, psi=r.psi)
+            out = outs.get(r.rid) if outs else None
+            srv.submit(r.op, a, b, mode=r.mode, q=r.q, phi=r.phi, psi=r.psi, out=out)
         srv.drain()
         return srv.stats()
 
-    srv = Server(hbm_budget=64 << 30, slots=4)
+    srv = Server(hbm_budget=budget, slots=slots)
+    tuning = {"table": None, "mode": "off"}
+    if tune_save:
+        # one untimed pass with autotuning on: every new shape class is tuned
+        # at its first request, then the table is saved and frozen
+        T.set_autotune("on")
+        t1 = time.perf_counter()
+        run(srv, reqs)
+        T.autotune_save(tune_save)
+        T.set_autotune("frozen")
+        tuning = {"table": os.path.relpath(tune_save, HERE), "mode": "frozen",
+                  "tuned_in_s": round(time.perf_counter() - t1, 1)}
+        log("serve: tuned %d entries in %.1f s" % (T.autotune_entries(), time.perf_counter() - t1))
+    elif table and os.path.exists(table):
+        T.autotune_load(table)
+        T.set_autotune("frozen")
+        tuning = {"table": os.path.relpath(table, HERE), "mode": "frozen"}
+    tuning["entries"] = T.autotune_entries()
     run(srv, reqs[:300])  # warm-up: kernels, graphs, arena
     closed = run(srv, reqs)
     mu = closed["req_per_s"]
-    print("serve: closed loop %.0f req/s" % mu, file=sys.stderr, flush=True)
-    opened = run(srv, reqs, rate=0.8 * mu)
-    print("serve: open loop p50 %.3f ms p99 %.3f ms" % (opened["p50_ms"], opened["p99_ms"]),
-          file=sys.stderr, flush=True)
+    log("serve: closed loop %.0f req/s" % mu)
+    # results kept from the headline (0.8 x) run, compared bitwise with the
+    # checked results below
+    tie = {r.rid: _result_tensor(T, r, operands) for r in reqs if r.rid % SERVE_TIE_EVERY == 0}
+    opened = {}
+    for f in SERVE_RATES:
+        st = run(srv, reqs, rate=f * mu, outs=tie if f == 0.8 else None)
+        opened["%.2f" % f] = st
+        log("serve: open loop %.2f x: p50 %.3f ms p99 %.3f ms, %.0f req/s" % (f, st["p50_ms"], st["p99_ms"],
+                                                                             st["req_per_s"]))
+    check_res = None
+    if check:
+        check_res = served_check(srv, reqs, operands, tie, log)
     srv.close()
+    del tie
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
 
     # plain per-call FP64: the same requests, one synchronous call each
-    n64 = min(len(reqs), 3000)
     cache = {}
 
     def f64(t):
@@ -299,8 +356,7 @@ def serve_bench(args):
             cache[key] = T.scale(1.0, t, dtype=torch.float64)
         return cache[key]
 
-    sub = reqs[:n64]
-    ops64 = [(r, f64(operands(r, "f32")[0]), f64(operands(r, "f32")[1])) for r in sub]
+    ops64 = [(r, f64(operands(r, "f32")[0]), f64(operands(r, "f32")[1])) for r in reqs]
     torch.cuda.synchronize()
     lat = []
     t_s = time.perf_counter()
@@ -314,26 +370,217 @@ def serve_bench(args):
             T.ttt(a, b, r.q, r.phi, r.psi)
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - t1)
-    plain_rps = n64 / (time.perf_counter() - t_s)
+    plain_rps = len(ops64) / (time.perf_counter() - t_s)
+    del ops64, cache
+    torch.cuda.empty_cache()
     lat.sort()
+    log("serve: plain FP64 per call %.0f req/s" % plain_rps)
+    rnd = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+    return {
+        "requests": len(reqs),
+        "slots": slots,
+        "output_budget_GB": budget >> 30,
+        "closed_loop": rnd(closed),
+        "open_loop": {k: rnd(v) for k, v in opened.items()},
+        "headline_rate": "0.80",
+        "kernel_choice": tuning,
+        "plain_fp64_per_call": {"requests": len(reqs), "req_per_s": round(plain_rps, 1),
+                                "p50_ms": round(lat[len(lat) // 2] * 1e3, 3),
+                                "p99_ms": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))] * 1e3, 3)},
+        "speedup_vs_plain_fp64": round(mu / plain_rps, 2),
+        "errors_vs_oracle": check_res,
+    }
+
+
+def _result_tensor(T, r, operands):
+    """A device tensor for request r's result (the layout the server uses)."""
+    import torch
+
+    a, b = operands(r)
+    acc = T.acc_dtype(a.dtype)
+    if r.op == "ttv":
+        shape = tuple(a.shape[: r.mode - 1]) + tuple(a.shape[r.mode:])
+        lay = [k if k < r.mode else k - 1 for k in T.layout_of(a) if k != r.mode]
+    elif r.op == "ttm":
+        shape = list(a.shape)
+        shape[r.mode - 1] = b.shape[0]
+        lay = T.layout_of(a)
+    else:
+        shape = T.ttt_shape(tuple(a.shape), tuple(b.shape), r.q, r.phi, r.psi)
+        lay = None
+    return torch.full(tuple(shape), float("nan"), dtype=acc, device=a.device) if lay is None else \
+        T.empty(tuple(shape), lay, acc, a.device).fill_(float("nan"))
+
+
+def _subgrid(r, a_shape, b_shape, g):
+    """Index subsets of the free modes of request r so that the oracle's work
+    on the sub-grid stays within CHECK_MACS (every index when the whole result
+    fits).  Returns ({A mode: indices}, {B mode: indices}, whole)."""
+    import numpy as np
+
+    p = len(a_shape)
+    if r.op == "ttv":
+        k = a_shape[r.mode - 1]
+        free = {("a", d): a_shape[d] for d in range(p) if d != r.mode - 1}
+    elif r.op == "ttm":
+        k = a_shape[r.mode - 1]
+        free = {("a", d): a_shape[d] for d in range(p) if d != r.mode - 1}
+        free[("b", 0)] = b_shape[0]
+    else:
+        ra = p - r.q
+        k = int(np.prod([a_shape[m - 1] for m in r.phi[ra:]], dtype=np.int64))
+        free = {("a", m - 1): a_shape[m - 1] for m in r.phi[:ra]}
+        sb = len(b_shape) - r.q
+        free.update({("b", m - 1): b_shape[m - 1] for m in r.psi[:sb]})
+    sizes = dict(free)
+    want = max(1, CHECK_MACS // max(1, k))
+    while int(np.prod(list(sizes.values()) or [1], dtype=np.int64)) > want:
+        big = max(sizes, key=lambda d: sizes[d])
+        if sizes[big] == 1:
+            break
+        sizes[big] = (sizes[big] + 1) // 2
+    whole = all(sizes[d] == free[d] for d in free)
+    sel_a, sel_b = {}, {}
+    for d, n in free.items():
+        idx = np.arange(n) if sizes[d] == n else np.sort(g.choice(n, size=sizes[d], replace=False))
+        (sel_a if d[0] == "a" else sel_b)[d[1]] = idx
+    return sel_a, sel_b, whole
+
+
+def _gather(t, sel):
+    """t restricted to the given indices per dim (on the device), as float64 numpy."""
+    import torch
+
+    for d, idx in sel.items():
+        t = t.index_select(d, torch.as_tensor(idx, device=t.device))
+    return t.double().cpu().numpy()
+
+
+def _check_one(r, got, operands, g):
+    """Normwise error of one served result against the FP64 oracle on a seeded
+    sub-grid (_subgrid); for a BF16 request also the kernel-only error (oracle
+    on the BF16 operands).  Returns (error, kernel-only error or None, whole)."""
+    import numpy as np
+
+    import oracle
+
+    a32, b32 = operands(r, "f32")
+    sel_a, sel_b, whole = _subgrid(r, tuple(a32.shape), tuple(b32.shape), g)
+    if r.op == "ttv":
+        ref = lambda A, B: oracle.ttv(A, B, r.mode)
+        cs = {(d if d < r.mode - 1 else d - 1): v for d, v in sel_a.items()}
+    elif r.op == "ttm":
+        ref = lambda A, B: oracle.ttm(A, B, r.mode)
+        cs = dict(sel_a)
+        cs[r.mode - 1] = sel_b[0]
+    else:
+        ref = lambda A, B: oracle.ttt(A, B, r.q, r.phi, r.psi)
+        ra = len(a32.shape) - r.q
+        cs = {k: sel_a[m - 1] for k, m in enumerate(r.phi[:ra])}
+        cs.update({ra + k: sel_b[m - 1] for k, m in enumerate(r.psi[:len(b32.shape) - r.q])})
+    G = _gather(got, cs)
+
+    def rel(R):
+        R = np.asarray(R)
+        nr = float(np.linalg.norm(R.ravel()))
+        d = float(np.linalg.norm((G - R).ravel()))
+        return d / nr if nr > 0 else d
+
+    e = rel(ref(_gather(a32, sel_a), _gather(b32, sel_b)))
+    ek = None
+    if r.dtype != "f32":
+        a16, b16 = operands(r)
+        ek = rel(ref(_gather(a16, sel_a), _gather(b16, sel_b)))
+    return e, ek, whole
+
+
+def served_check(srv, reqs, operands, tie, log, chunk=256):
+    """Every served request once more through the same server (closed loop,
+    caller-owned outputs), each result compared with the FP64 oracle on a
+    seeded sub-grid of its outputs (the whole result when its oracle work is at
+    most CHECK_MACS multiply-adds); results kept from the headline open-loop
+    run must equal these bit for bit (a request's kernel does not depend on
+    the mix).  BF16 requests are measured end to end (oracle on the FP32 values
+    the BF16 operands were rounded from) and kernel-only (oracle on the BF16
+    values)."""
+    import numpy as np
+    import torch
+
+    import paper_1711_10912_amd as T
+
+    t0 = time.perf_counter()
+    g = np.random.default_rng(171110912 + 6)
+    errs = {"f32": [], "bf16": [], "bf16_kernel": []}
+    whole = 0
+    tie_equal = tie_total = 0
+    over = []
+    for c0 in range(0, len(reqs), chunk):
+        part = reqs[c0:c0 + chunk]
+        outs = {r.rid: _result_tensor(T, r, operands) for r in part}
+        srv.reset_stats()
+        for r in part:
+            a, b = operands(r)
+            srv.submit(r.op, a, b, mode=r.mode, q=r.q, phi=r.phi, psi=r.psi, out=outs[r.rid])
+        srv.drain()
+        st = srv.stats()
+        if st["errors"]:
+            raise RuntimeError("served check: %d requests failed" % st["errors"])
+        for r in part:
+            got = outs[r.rid]
+            if r.rid in tie:
+                tie_total += 1
+                tie_equal += int(torch.equal(got.view(torch.int32), tie[r.rid].view(torch.int32)))
+            e, ek, w = _check_one(r, got, operands, g)
+            whole += int(w)
+            errs["f32" if r.dtype == "f32" else "bf16"].append(e)
+            if ek is not None:
+                errs["bf16_kernel"].append(ek)
+            bar = 1e-5 if r.dtype == "f32" else 2e-2
+            if e > bar:
+                over.append({"rid": r.rid, "op": r.op, "dtype": r.dtype, "err": e})
+        del outs
+        if (c0 // chunk) % 8 == 0:
+            log("serve check: %d / %d results (%.0f s)" % (c0 + len(part), len(reqs), time.perf_counter() - t0))
+
+    def summ(v):
+        v = np.sort(np.asarray(v))
+        if v.size == 0:
+            return None
+        return {"results": int(v.size), "max": float(v[-1]), "p99": float(v[min(v.size - 1, int(0.99 * v.size))]),
+                "median": float(v[v.size // 2])}
+
+    return {
+        "measure": "normwise ||C - C*|| / ||C*|| per result against the FP64 oracle, on a seeded sub-grid "
+                   "of each result's outputs (whole result when its oracle work is <= %d multiply-adds)" % CHECK_MACS,
+        "results_checked": len(reqs),
+        "checked_whole": whole,
+        "f32": summ(errs["f32"]),
+        "bf16_end_to_end": summ(errs["bf16"]),
+        "bf16_kernel_only": summ(errs["bf16_kernel"]),
+        "bars": {"f32": 1e-5, "bf16": 2e-2},
+        "over_bar": over[:20],
+        "n_over_bar": len(over),
+        "headline_run_results_bitwise_equal": "%d/%d" % (tie_equal, tie_total),
+        "seconds": round(time.perf_counter() - t0, 1),
+    }
+
+
+def serve_bench(args):
+    """The served stream alone (req/s as the value)."""
+    sv = served_measure(args.requests, check=not args.no_serve_check, tune_save=args.autotune_save)
     return {
         "metric": METRIC,
-        "value": round(mu, 1),
+        "value": round(sv["closed_loop"]["req_per_s"], 1),
         "unit": "req/s (closed-loop capacity of the served mixed stream)",
         "n_gpus": 1, "steps": 1, "warmup": 1,
-        "ms_per_step": round(len(reqs) / mu * 1e3, 3),
+        "ms_per_step": round(sv["requests"] / sv["closed_loop"]["req_per_s"] * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32,bf16 (per request tag), f32 accumulation",
         "data": "synthetic request stream (seeded): orders 2..6, log-uniform extents 8..512, <=2^24 "
                 "elements, 40/40/20 TTV/TTM/TTT, resident operand pool of 1024 tensors",
-        "config": {"workload": "served mixed stream, %d requests" % len(reqs), "slots": 4,
-                   "output_budget_GB": 64},
-        "served_closed_loop": closed,
-        "served_open_loop_0p8": opened,
-        "plain_fp64_per_call": {"requests": n64, "req_per_s": round(plain_rps, 1),
-                                "p50_ms": round(lat[len(lat) // 2] * 1e3, 3),
-                                "p99_ms": round(lat[int(0.99 * len(lat))] * 1e3, 3)},
-        "speedup_vs_plain_fp64": round(mu / plain_rps, 2),
+        "config": {"workload": "served mixed stream, %d requests" % sv["requests"], "slots": sv["slots"],
+                   "output_budget_GB": sv["output_budget_GB"]},
+        "served": sv,
     }
 
 
@@ -645,6 +892,11 @@ def main():
                          "with the package")
     ap.add_argument("--autotune-save", default="", help="write the table after the first warmup step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-stream section of the sweep run")
+    ap.add_argument("--families", default="",
+                    help="comma-separated case families to keep (ttv,ttm,ttt,outer,inner,norm,add; profiling runs)")
+    ap.add_argument("--no-serve-check", action="store_true",
+                    help="skip the offline oracle check of the served results")
     ap.add_argument("--cases-out", default="", help="write per-case timings (JSON lines) here")
     ap.add_argument("--workload", default="sweep", choices=("sweep", "serve", "drivers", "views"),
                     help="sweep: the order-p TTV/TTM sweep + TTT (default); serve: the served "
@@ -691,6 +943,9 @@ def main():
 
     dev = torch.device("cuda:0")
     cases, keep, outbuf = build_cases(T, torch, dev, quick=args.quick)
+    if args.families:
+        fams = set(args.families.split(","))
+        cases = [c for c in cases if c.family in fams]
     torch.cuda.synchronize()
     print("bench: %d calls per step" % len(cases), file=sys.stderr, flush=True)
     # Autotuning (kernel choice per call shape) happens in the first warmup
@@ -797,9 +1052,16 @@ def main():
                                     "TFLOP/s": round(c.flops / (avg * 1e-3) / 1e12, 3),
                                     "roofline_frac": round(c.ideal_s() / (avg * 1e-3), 4)}) + "\n")
 
+    n_calls = len(cases)
+    del cases, keep, outbuf, ev
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    served = None
+    if not args.no_serve:
+        served = served_measure(args.requests, check=not args.no_serve_check)
+
     cpu = None
     if not args.no_cpu_baseline:
-        del keep, outbuf
         cpu = cpu_baseline_both()
 
     out = {
@@ -817,8 +1079,12 @@ def main():
         "data": "synthetic (seeded uniform[-1,1] / normal(0,1) on device)",
         "config": {"workload": "order-p sweep p=3..7 (406^3,90^4,36^5,20^6,13^7), every mode, first+last order, "
                                "f64+f32: TTV, TTM m=16/64/256, inner, norm, add; plus TTT (96,80,64,48)x(64,48,120) "
-                               "A{3,4}<->B{1,2}, 3 A layouts, f32/bf16/f16" + (" [quick: p=3,7 only]" if args.quick else ""),
-                   "calls_per_step": len(cases)},
+                               "A{3,4}<->B{1,2}, 3 A layouts, f32/bf16/f16; outer product (512,128)x(64,40) f64+f32"
+                               + (" [quick: p=3,7 only]" if args.quick else "")
+                               + (" [families: %s]" % args.families if args.families else ""),
+                   "served": None if args.no_serve else "mixed stream of %d requests (see the served object)"
+                   % args.requests,
+                   "calls_per_step": n_calls},
         "roofline_frac_step": round(tot_ideal / (ms_per_step * 1e-3), 4),
         "autotune": {"mode": tune, "preloaded": preloaded, "entries": T.autotune_entries(),
                      "table": os.path.relpath(args.autotune_table, HERE) if preloaded else None,
@@ -826,6 +1092,7 @@ def main():
         "roofline": roof,
         "breakdown": breakdown,
         "kernels": kernels,
+        "served": served,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

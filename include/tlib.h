@@ -126,9 +126,10 @@ int tlib_ttt(const tlib_tensor* A, const tlib_tensor* B, int32_t q,
 /* tlib_ttt for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * same operation, arguments and errors as tlib_ttt, but no workspace.  Its
- * split-K partials live in a static device array of
- * TLIB_NOALLOC_SCRATCH_BYTES per GPU, part of the library's code object and
- * held until the process ends; the split is bounded by that size (a product
+ * split-K partials (and the split's per-tile counters, 64 KiB) live in a
+ * static device array of TLIB_NOALLOC_SCRATCH_BYTES per GPU, part of the
+ * library's code object and held until the process ends; the split is
+ * bounded by that size (a product
  * whose single slice would not fit runs unsplit, so no size is refused; a
  * plan that needed more would return TLIB_ENOMEM before launching).  The tile
  * is the planner's rule (no autotuning).  The call allocates nothing and never
@@ -148,6 +149,15 @@ int tlib_inner(const tlib_tensor* A, const tlib_tensor* B, double* out_dev, void
 
 /* Frobenius norm sqrt(<A, A>) (Sec. 5.2 Table 3); one double to out_dev (device). */
 int tlib_norm(const tlib_tensor* A, double* out_dev, void* stream);
+
+/* Normalisation step of the higher-order power method (Sec. 5.2):
+ * *norm_dev = ||A||_F (FP64, as tlib_norm) and C = A / ||A||_F, the quotient
+ * formed in FP64 and rounded once to C's dtype.  norm_dev is device memory
+ * and the division reads it there, so the pair runs without a host round
+ * trip.  C has A's shape, any dtype and injective strides; C may be A itself
+ * (same pointer, strides and dtype), any other overlap is TLIB_EALIAS.  Uses
+ * the stream's workspace for the norm's partial sums. */
+int tlib_normalize(const tlib_tensor* A, double* norm_dev, const tlib_tensor* C, void* stream);
 
 /* C = alpha A + beta B (Sec. 5.1 Eq. transform with a scaled sum).  A, B, C
  * have equal shapes and independent layouts and share one dtype.  C may be
@@ -182,24 +192,33 @@ int tlib_transpose(const tlib_tensor* A, const int32_t* tau, const tlib_tensor* 
 int tlib_times_vectors(const tlib_tensor* A, const tlib_tensor* const* us, int32_t r,
                        const tlib_tensor* c, void* stream);
 
-/* ---- Grouped launch of many small TTV / TTM requests ------------------------
- * A request is a TTV (op 0, B = the vector b) or a TTM (op 1, B = the matrix)
- * with the same argument rules as tlib_ttv / tlib_ttm.  tlib_batch_plan
- * validates n requests and writes a work table into caller-provided host
- * memory of tlib_batch_table_bytes(n) bytes; the caller copies the table to
- * device memory and runs it with tlib_batch_run, which enqueues one kernel
- * whose arguments depend only on the table's device address and the grid:
- * the launch can be captured in a HIP graph once and replayed after the
- * table's contents change.  Requests must not alias each other's outputs.
- * A request whose tensors do not collapse to one (lo, k, hi) stride form is
- * rejected with TLIB_ESTRIDE and its index in *bad (run it with tlib_ttv /
- * tlib_ttm instead).  *units receives the number of 256-output work units. */
+/* ---- Grouped launch of many small TTV / TTM / TTT requests -------------------
+ * A request is a TTV (op 0, B = the vector b, mode = m), a TTM (op 1, B = the
+ * matrix, mode = m) or a TTT (op 2, q, phi, psi) with the same argument rules
+ * as tlib_ttv / tlib_ttm / tlib_ttt.  tlib_batch_plan validates n requests and
+ * writes a work table into caller-provided host memory of
+ * tlib_batch_table_bytes(n) bytes; the caller copies the table to device
+ * memory and runs it with tlib_batch_run, which enqueues one kernel whose
+ * arguments depend only on the table's device address and the grid: the
+ * launch can be captured in a HIP graph once and replayed after the table's
+ * contents change.  TTV requests run one thread per output; TTM and TTT
+ * requests run as 16 x 64 tiles of C on matrix cores.  Each request's result
+ * depends only on the request, never on the rest of the batch.  Requests must
+ * not alias each other's outputs.  A request whose index groups do not
+ * collapse to at most four (extent, stride) pairs each (and 2^31 indices) is
+ * rejected with TLIB_ESTRIDE and its index in *bad (run it with the single
+ * entry points instead; tlib_request_groupable tells in advance).  *units
+ * receives the number of work units. */
 typedef struct {
-    int32_t op;              /* 0 = TTV, 1 = TTM */
-    int32_t mode;            /* m, 1-based */
+    int32_t op;              /* 0 = TTV, 1 = TTM, 2 = TTT */
+    int32_t mode;            /* TTV / TTM: m, 1-based */
     const tlib_tensor* A;
     const tlib_tensor* B;
     const tlib_tensor* C;
+    int32_t q;               /* TTT: number of contracted pairs */
+    int32_t reserved;
+    const int32_t* phi;      /* TTT: length order(A), 1-based (host memory) */
+    const int32_t* psi;      /* TTT: length order(B), 1-based (host memory) */
 } tlib_request;
 
 size_t tlib_batch_table_bytes(int32_t n);
@@ -207,6 +226,8 @@ int tlib_batch_plan(const tlib_request* reqs, int32_t n, void* table_host, size_
                     int64_t* units, int32_t* bad);
 /* table_dev: device copy of a planned table; grid: persistent workgroups (0 = 1024). */
 int tlib_batch_run(const void* table_dev, int32_t grid, void* stream);
+/* 1 if the request is valid and fits the grouped kernel, 0 otherwise (host only). */
+int tlib_request_groupable(const tlib_request* r);
 
 /* ---- Request server (continuous batching on one GPU) ------------------------
  * tlib_server_create starts a scheduler thread with `slots` HIP streams and an
@@ -214,9 +235,9 @@ int tlib_batch_run(const void* table_dev, int32_t grid, void* stream);
  * results in flight; 0 = outputs always supplied by the caller).  Requests are
  * admitted in arrival order while a slot is free and the output fits; requests
  * that arrive while others run start as soon as a slot and memory free up.
- * Consecutive TTV/TTM requests of at most `group_macs` multiply-adds are fused
- * (up to `group_max`) into one grouped launch replayed from a per-slot HIP
- * graph.  A request's kernel depends only on the request, so its result is the
+ * Consecutive TTV/TTM/TTT requests of at most `group_macs` multiply-adds that
+ * fit the grouped kernel (tlib_request_groupable) are fused (up to
+ * `group_max`) into one grouped launch replayed from a per-slot HIP graph.  A request's kernel depends only on the request, so its result is the
  * same alone and in any mix.
  * tlib_server_submit: op 0 = TTV (B = b), 1 = TTM (B = matrix), 2 = TTT (q,
  * phi, psi as tlib_ttt); A and B are caller-owned device tensors that must be

@@ -19,7 +19,7 @@ from . import _lib
 from ._lib import TlibError
 
 __all__ = [
-    "ttv", "ttm", "ttt", "ttt_noalloc", "inner", "norm", "add", "scale", "transpose", "times_tensor",
+    "ttv", "ttm", "ttt", "ttt_noalloc", "inner", "norm", "normalize", "add", "scale", "transpose", "times_tensor",
     "times_vectors", "strides", "layout_of", "empty", "TlibError", "plan", "hopm", "tucker",
     "set_autotune", "autotune_entries", "autotune_clear", "autotune_save", "autotune_load",
     "workspace_reserve", "workspace_size", "workspace_release",
@@ -195,6 +195,20 @@ def norm(A, out=None):
         out = torch.empty((), dtype=torch.float64, device=A.device)
     _lib.check(_lib.lib().tlib_norm(ctypes.byref(_desc(A)), ctypes.c_void_p(out.data_ptr()), _stream(A)))
     return out
+
+
+def normalize(A, out=None, norm_out=None, dtype=None):
+    """out = A / ||A||_F with the FP64 norm written to norm_out (a 0-d float64
+    device tensor), both on the device (Sec. 5.2, the normalisation of the
+    higher-order power method).  out may be A itself.  Returns (out, norm_out)."""
+    torch = _t()
+    if norm_out is None:
+        norm_out = torch.empty((), dtype=torch.float64, device=A.device)
+    if out is None:
+        out = empty(A.shape, layout_of(A), dtype or A.dtype, A.device)
+    _lib.check(_lib.lib().tlib_normalize(ctypes.byref(_desc(A)), ctypes.c_void_p(norm_out.data_ptr()),
+                                         ctypes.byref(_desc(out)), _stream(A)))
+    return out, norm_out
 
 
 def add(alpha: float, A, beta: float, B, out=None, layout=None):

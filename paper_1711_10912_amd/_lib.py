@@ -16,9 +16,9 @@ OK, EINVAL, ESHAPE, EMODE, EDTYPE, EALIAS, ESTRIDE, ENOMEM, EHIP = range(9)
 MAX_ORDER = 16
 
 EXPORTS = (
-    "tlib_ttv", "tlib_ttm", "tlib_ttm2", "tlib_ttt", "tlib_ttt_noalloc", "tlib_inner", "tlib_norm", "tlib_add", "tlib_scale",
+    "tlib_ttv", "tlib_ttm", "tlib_ttm2", "tlib_ttt", "tlib_ttt_noalloc", "tlib_inner", "tlib_norm", "tlib_normalize", "tlib_add", "tlib_scale",
     "tlib_transpose", "tlib_times_vectors", "tlib_batch_table_bytes", "tlib_batch_plan", "tlib_batch_run",
-    "tlib_request_check", "tlib_server_create", "tlib_server_submit", "tlib_server_drain", "tlib_server_stats",
+    "tlib_request_check", "tlib_request_groupable", "tlib_server_create", "tlib_server_submit", "tlib_server_drain", "tlib_server_stats",
     "tlib_server_result", "tlib_server_reset_stats", "tlib_server_destroy",
     "tlib_strides_from_layout", "tlib_last_error", "tlib_strerror", "tlib_set_plan_only",
     "tlib_last_plan", "tlib_set_autotune", "tlib_autotune_entries", "tlib_autotune_clear", "tlib_autotune_save",
@@ -44,6 +44,10 @@ class Request(ctypes.Structure):
         ("A", ctypes.POINTER(TensorDesc)),
         ("B", ctypes.POINTER(TensorDesc)),
         ("C", ctypes.POINTER(TensorDesc)),
+        ("q", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("phi", ctypes.POINTER(ctypes.c_int32)),
+        ("psi", ctypes.POINTER(ctypes.c_int32)),
     ]
 
 
@@ -82,6 +86,7 @@ def lib():
         L.tlib_ttt_noalloc.argtypes = [P, P, ctypes.c_int32, i32p, i32p, P, vp]
         L.tlib_inner.argtypes = [P, P, vp, vp]
         L.tlib_norm.argtypes = [P, vp, vp]
+        L.tlib_normalize.argtypes = [P, vp, P, vp]
         L.tlib_add.argtypes = [ctypes.c_double, P, ctypes.c_double, P, P, vp]
         L.tlib_scale.argtypes = [ctypes.c_double, P, P, vp]
         L.tlib_transpose.argtypes = [P, i32p, P, vp]
@@ -95,6 +100,8 @@ def lib():
         L.tlib_batch_run.restype = ctypes.c_int
         L.tlib_request_check.argtypes = [ctypes.c_int32, P, P, ctypes.c_int32, ctypes.c_int32, i32p, i32p, P]
         L.tlib_request_check.restype = ctypes.c_int
+        L.tlib_request_groupable.argtypes = [ctypes.POINTER(Request)]
+        L.tlib_request_groupable.restype = ctypes.c_int
         L.tlib_plan_cache_stats.argtypes = [i64p, i64p, i64p]
         L.tlib_plan_cache_stats.restype = None
         L.tlib_plan_cache_clear.argtypes = []
@@ -121,7 +128,7 @@ def lib():
         L.tlib_server_reset_stats.restype = None
         L.tlib_server_destroy.argtypes = [vp]
         L.tlib_server_destroy.restype = None
-        for f in ("tlib_ttv", "tlib_ttm", "tlib_ttm2", "tlib_ttt", "tlib_ttt_noalloc", "tlib_inner", "tlib_norm", "tlib_add",
+        for f in ("tlib_ttv", "tlib_ttm", "tlib_ttm2", "tlib_ttt", "tlib_ttt_noalloc", "tlib_inner", "tlib_norm", "tlib_normalize", "tlib_add",
                   "tlib_scale", "tlib_transpose", "tlib_times_vectors", "tlib_strides_from_layout"):
             getattr(L, f).restype = ctypes.c_int
         L.tlib_last_error.restype = ctypes.c_char_p

@@ -260,6 +260,22 @@ bool capturing(hipStream_t s) {
 static constexpr size_t WS_ALIGN = 256;
 static size_t ws_round(size_t b) { return (b + WS_ALIGN - 1) / WS_ALIGN * WS_ALIGN; }
 
+// A new buffer: its counter region (the last WS_COUNTER_BYTES) starts at zero.
+// The fill runs on the stream that allocates, never while it captures.
+static void* ws_alloc(size_t bytes, hipStream_t s) {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (hipMemsetAsync(static_cast<char*>(p) + bytes - WS_COUNTER_BYTES, 0, WS_COUNTER_BYTES, s) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(p);
+        return nullptr;
+    }
+    return p;
+}
+
 void* WsCtx::take(size_t bytes) {
     bytes = ws_round(bytes);
     if (bytes == 0) return base ? base + used : nullptr;
@@ -271,19 +287,17 @@ void* WsCtx::take(size_t bytes) {
         WsBuf& e = g_ws[{dev, s}];
         if (!e.ptr) {
             if (capturing(s)) return nullptr;  // no allocation while a graph is captured
-            const size_t want = std::max({ws_round(hint), used + bytes, size_t(TLIB_WORKSPACE_DEFAULT_BYTES)});
-            void* p = nullptr;
-            if (hipMalloc(&p, want) != hipSuccess) {
-                (void)hipGetLastError();
-                return nullptr;
-            }
+            const size_t want = std::max({ws_round(hint) + WS_COUNTER_BYTES, used + bytes + WS_COUNTER_BYTES,
+                                          size_t(TLIB_WORKSPACE_DEFAULT_BYTES)});
+            void* p = ws_alloc(want, s);
+            if (!p) return nullptr;
             e.ptr = static_cast<char*>(p);
             e.bytes = want;
         }
         base = e.ptr;
         size = e.bytes;
     }
-    if (used + bytes > size) return nullptr;
+    if (used + bytes > avail_total()) return nullptr;
     void* p = base + used;
     used += bytes;
     return p;
@@ -312,7 +326,7 @@ static int ws_fail(const WsCtx& ws, size_t bytes, const char* op) {
 
 enum LaunchKind {
     LK_NONE = 0, LK_TTV_COLW, LK_TTV_COL, LK_TTV_SLAB, LK_TTV_FIBER, LK_TTV_GENERIC,
-    LK_GEMM, LK_GEMM_GENERIC, LK_TTM_STREAM, LK_TTM_ROWS
+    LK_GEMM, LK_GEMM_GENERIC, LK_TTM_STREAM, LK_TTM_ROWS, LK_OUTER
 };
 
 struct Launch {
@@ -328,6 +342,7 @@ struct Launch {
     GemmParams gemm{};
     TtmParams tstr{};
     TtmRowParams trow{};
+    OuterParams outer{};
     std::string note;
 };
 
@@ -359,6 +374,11 @@ static int exec_launch(const Launch& L, const void* in0, const void* in1, void* 
         P.Y = L.xsrc ? in0 : in1;
         P.C = out;
         P.part = w;
+        // split-K sums in the kernel (the last slice of a tile to finish)
+        // when the buffer's counters cover every tile
+        P.cnt = nullptr;
+        if (P.ksplit > 1 && ws.base && int64_t(P.tiles_m) * P.tiles_n <= int64_t(WS_COUNTER_BYTES / 4))
+            P.cnt = ws.counters();
         rc = launch_gemm(L.dtype, L.i0, P, s);
     } else if (L.kind == LK_GEMM_GENERIC) {
         rc = launch_gemm_generic(L.dtype, L.xsrc ? in1 : in0, L.xsrc ? in0 : in1, out, L.gd[0], L.gd[1], L.gd[2], s);
@@ -368,6 +388,12 @@ static int exec_launch(const Launch& L, const void* in0, const void* in1, void* 
         T.Y = in0;
         T.C = out;
         rc = launch_ttm_stream(L.dtype, T, L.i0, L.i1, true, L.i2, s);
+    } else if (L.kind == LK_OUTER) {
+        OuterParams O = L.outer;
+        O.X = L.xsrc ? in1 : in0;
+        O.Y = L.xsrc ? in0 : in1;
+        O.C = out;
+        rc = launch_outer(L.dtype, O, s);
     } else if (L.kind == LK_TTM_ROWS) {
         TtmRowParams R = L.trow;
         R.X = in1;
@@ -650,25 +676,111 @@ static void key_ten(std::string& k, const Ten& t) {
     }
 }
 
+// Shape class of a call: the features the kernel choice follows, so that a
+// choice tuned on one shape serves the other shapes of its class (a served
+// stream rarely repeats an exact shape).  Extents enter as base-4 log buckets.
+static int lg4(int64_t x) {
+    int b = 0;
+    while (x >= 4) {
+        x >>= 2;
+        ++b;
+    }
+    return b;
+}
+
+static int64_t min_stride(const Ten& t, const int* modes, int nm) {
+    int64_t m = INT64_MAX;
+    for (int i = 0; i < nm; ++i)
+        if (t.n[modes[i]] > 1) m = std::min(m, t.w[modes[i]]);
+    return m;
+}
+
+// TTM: dtype; whether mode m has A's smallest stride (contiguous k-fibers)
+// and C's smallest stride (C contiguous along j); buckets of n_m, of B's rows,
+// of the columns N / n_m and of n_lo (the extent below mode m in A's memory).
+static std::string ttm_class_key(const Ten& a, const Ten& bm, const Ten& c, int mi) {
+    int64_t n_lo = 1, cols = 1;
+    bool jmin = true;
+    for (int r = 0; r < a.p; ++r) {
+        if (r == mi) continue;
+        cols *= a.n[r];
+        if (a.n[r] > 1 && a.w[r] < a.w[mi]) n_lo *= a.n[r];
+        if (c.n[r] > 1 && c.w[r] < c.w[mi]) jmin = false;
+    }
+    std::string k = "class:ttm";
+    key_int(k, a.dtype);
+    key_int(k, n_lo == 1);
+    key_int(k, jmin);
+    key_int(k, lg4(a.n[mi]));
+    key_int(k, lg4(bm.n[0]));
+    key_int(k, lg4(cols));
+    key_int(k, lg4(n_lo));
+    return k;
+}
+
+// TTT: dtype; whether the contracted modes hold the smallest stride of A and
+// of B, whether C's smallest stride is among the free modes of A; buckets of
+// M, N and K.
+static std::string ttt_class_key(const Ten& a, const Ten& b, const Ten& c, int q, const int32_t* phi,
+                                 const int32_t* psi) {
+    const int r = a.p - q, s = b.p - q;
+    int fa[MAXP], ka[MAXP], fb[MAXP], kb[MAXP], ca[MAXP], cb[MAXP];
+    int64_t M = 1, N = 1, K = 1;
+    for (int i = 0; i < r; ++i) {
+        fa[i] = phi[i] - 1;
+        M *= a.n[fa[i]];
+        ca[i] = i;
+    }
+    for (int i = 0; i < q; ++i) {
+        ka[i] = phi[r + i] - 1;
+        kb[i] = psi[s + i] - 1;
+        K *= a.n[ka[i]];
+    }
+    for (int i = 0; i < s; ++i) {
+        fb[i] = psi[i] - 1;
+        N *= b.n[fb[i]];
+        cb[i] = r + i;
+    }
+    std::string k = "class:ttt";
+    key_int(k, a.dtype);
+    key_int(k, min_stride(a, ka, q) < min_stride(a, fa, r));
+    key_int(k, min_stride(b, kb, q) < min_stride(b, fb, s));
+    key_int(k, min_stride(c, ca, r) < min_stride(c, cb, s));
+    key_int(k, lg4(M));
+    key_int(k, lg4(N));
+    key_int(k, lg4(K));
+    return k;
+}
+
 // *settled: the launch the call ended with is the key's lasting choice (the
 // planner's rule with autotuning off or frozen, a stored pick, or a pick just
 // tuned), so a plan cache may keep it; false when tuning was due but could
 // not run (plan-only mode, a capturing stream).
+// A shape without its own entry takes the entry of its class (ckey) when the
+// table has one; tuning a new shape stores its pick under both keys (the class
+// entry only if the class has none yet).
 template <class F>
-static int tuned(const std::string& key, const int* cands, int nc, hipStream_t s, F&& run, bool* settled) {
+static int tuned(const std::string& key, const std::string& ckey, const int* cands, int nc, hipStream_t s, F&& run,
+                 bool* settled) {
     *settled = true;
     const int mode = g_autotune.load();
     if (mode == TLIB_AUTOTUNE_OFF) return run(-1);
     int pick = PICK_NA;
+    bool by_class = false;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(key);
-        if (it != g_tune.end()) pick = it->second;
+        if (it != g_tune.end()) {
+            pick = it->second;
+        } else if ((it = g_tune.find(ckey)) != g_tune.end()) {
+            pick = it->second;
+            by_class = true;
+        }
     }
     if (pick != PICK_NA) {
         const int rc = run(pick);
         if (rc != PICK_NA) {
-            g_plan += " autotuned";
+            g_plan += by_class ? " autotuned(class)" : " autotuned";
             return rc;
         }
         return run(-1);
@@ -685,7 +797,7 @@ static int tuned(const std::string& key, const int* cands, int nc, hipStream_t s
     // warm every applicable candidate once, then time them round-robin
     // (three rounds, best of three per candidate) so that drift in clocks or
     // memory state during tuning hits every candidate alike
-    constexpr int MAXC = 16, ROUNDS = 3;
+    constexpr int MAXC = 32, ROUNDS = 3;
     int live[MAXC];
     float tmin[MAXC];
     int nl = 0;
@@ -718,6 +830,7 @@ static int tuned(const std::string& key, const int* cands, int nc, hipStream_t s
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune[key] = bp;
+        g_tune.emplace(ckey, bp);
     }
     const int rc = run(bp);
     if (rc == TLIB_OK) g_plan += " autotuned(new)";
@@ -730,7 +843,10 @@ static int tuned(const std::string& key, const int* cands, int nc, hipStream_t s
 // dm: M-group dims with strides (X, C); dn: N-group (Y, C); dk: K-group (X, Y).
 // x_is: X is operand 0 or 1 of the call.  ws_cap: scratch available when the
 // call brings a fixed buffer (SIZE_MAX: the stream's workspace).
-// tile_force >= 0 replaces the tile heuristic (autotuning candidates).
+// tile_force >= 0 replaces the tile heuristic (autotuning candidates):
+// tile_force % GT_COUNT is the tile, tile_force / GT_COUNT the split target
+// (0: about 1024 workgroups, 1: 512, 2: 256 -- fewer, deeper K slices and
+// fewer partials for products that would otherwise split K many ways).
 static int plan_gemm(int dtype, int x_is, const void* X, const void* Y, void* C, Dim* dm, int ndm, Dim* dn,
                      int ndn, Dim* dk, int ndk, const char* op, size_t ws_cap, Launch& L, int tile_force = -1) {
     L.op = op;
@@ -791,9 +907,10 @@ static int plan_gemm(int dtype, int x_is, const void* X, const void* Y, void* C,
             // Y as vectors along N: FP32/FP64, N's first dim of unit stride in
             // Y, K one dim; 16-byte vectors when K's stride keeps them
             // aligned, else 8-byte ones (FP32) when it keeps those aligned
+            // (16-bit: eight elements, stored transposed into the slice)
             P.syk = ndk == 1 ? dk[0].s[1] : 0;
             P.y_vec = 0;
-            if ((dtype == TLIB_F32 || dtype == TLIB_F64) && !P.y_kfast && ndk == 1 && ndn >= 1 && dn[0].s[0] == 1) {
+            if (!P.y_kfast && ndk == 1 && ndn >= 1 && dn[0].s[0] == 1) {
                 const int v16 = 16 / esize(dtype);
                 if (P.syk % v16 == 0 && (uintptr_t(Y) % 16) == 0) P.y_vec = v16;
                 else if (dtype == TLIB_F32 && P.syk % 2 == 0 && (uintptr_t(Y) % 8) == 0) P.y_vec = 2;
@@ -835,15 +952,19 @@ static int plan_gemm(int dtype, int x_is, const void* X, const void* Y, void* C,
         else if (N <= 128) tile = wide_acc ? GT_128x64 : GT_128x128;
         else tile = wide_acc ? GT_128x64 : GT_128x128;
         if (ntiles(tile) < 1024 && tile != GT_16x256 && ntiles(GT_64x64) > ntiles(tile)) tile = GT_64x64;
-        if (tile_force >= 0 && tile_force < GT_COUNT) tile = tile_force;
+        int split_target = 1024;
+        if (tile_force >= 0 && tile_force < 3 * GT_COUNT) {
+            tile = tile_force % GT_COUNT;
+            split_target = 1024 >> (tile_force / GT_COUNT);
+        }
         TileShape ts = tile_shape(tile);
         P.tiles_m = int32_t((M + ts.bm - 1) / ts.bm);
         P.tiles_n = int32_t((N + ts.bn - 1) / ts.bn);
         int64_t nt = int64_t(P.tiles_m) * P.tiles_n;
-        const int bk = dtype == TLIB_F64 ? 16 : 32;
+        const int bk = gemm_slice_k(dtype, tile);
         int ks = 1;
-        if (nt < 1024) {
-            int64_t want = (1024 + nt - 1) / nt;
+        if (nt < split_target) {
+            int64_t want = (split_target + nt - 1) / nt;
             int64_t maxk = std::max<int64_t>(1, K / (4 * bk));
             ks = int(std::min<int64_t>(std::min<int64_t>(want, maxk), 32));
         }
@@ -931,50 +1052,86 @@ static int check_ttm(const tlib_tensor* A, const tlib_tensor* B, int32_t m, cons
     return TLIB_OK;
 }
 
-// Collapse one TTV (is_ttm false) or TTM request into a BatchItem.
-static bool batch_item(const Ten& a, const Ten& b, int mi, const Ten& c, bool is_ttm, BatchItem& it) {
-    Dim d[MAXP];
-    int nd = 0;
-    for (int r = 0, k = 0; r < a.p; ++r) {
-        if (r == mi) continue;
-        d[nd++] = {a.n[r], {a.w[r], is_ttm ? c.w[r] : c.w[k], 0}};
-        ++k;
+// One grouped request as C[m, n] = sum_k X[m, k] Y[k, n] (a BatchItem).
+// TTV: X = b, Y = A, M = 1; TTM: X = B, Y = A; TTT: X = A, Y = B, the pairs
+// (phi_{r+k}, psi_{s+k}) forming K.  Returns false when a group does not
+// collapse to GMAXD dims and 2^31 indices.
+static int64_t min_c_stride(const Dim* d, int nd) {
+    int64_t m = INT64_MAX;
+    for (int i = 0; i < nd; ++i)
+        if (d[i].n > 1) m = std::min(m, d[i].s[1]);
+    return m;
+}
+
+static bool batch_item(int op, const Ten& a, const Ten& b, const Ten& c, int mi, int q, const int32_t* phi,
+                       const int32_t* psi, BatchItem& it) {
+    Dim dm[MAXP], dn[MAXP], dk[MAXP];
+    int ndm = 0, ndn = 0, ndk = 0;
+    const void* X = nullptr;
+    const void* Y = nullptr;
+    if (op == 0) {
+        for (int r = 0, k = 0; r < a.p; ++r) {
+            if (r == mi) continue;
+            dn[ndn++] = {a.n[r], {a.w[r], c.w[k++], 0}};
+        }
+        dk[ndk++] = {a.n[mi], {b.w[0], a.w[mi], 0}};
+        X = b.data;
+        Y = a.data;
+    } else if (op == 1) {
+        dm[ndm++] = {b.n[0], {b.w[0], c.w[mi], 0}};
+        for (int r = 0; r < a.p; ++r)
+            if (r != mi) dn[ndn++] = {a.n[r], {a.w[r], c.w[r], 0}};
+        dk[ndk++] = {a.n[mi], {b.w[1], a.w[mi], 0}};
+        X = b.data;
+        Y = a.data;
+    } else {
+        const int r = a.p - q, s = b.p - q;
+        for (int k = 0; k < r; ++k) dm[ndm++] = {a.n[phi[k] - 1], {a.w[phi[k] - 1], c.w[k], 0}};
+        for (int k = 0; k < s; ++k) dn[ndn++] = {b.n[psi[k] - 1], {b.w[psi[k] - 1], c.w[r + k], 0}};
+        for (int k = 0; k < q; ++k) dk[ndk++] = {a.n[phi[r + k] - 1], {a.w[phi[r + k] - 1], b.w[psi[s + k] - 1], 0}};
+        X = a.data;
+        Y = b.data;
     }
-    nd = coalesce(d, nd, 2, 0);
     it = BatchItem{};
     it.dtype = a.dtype;
-    it.A = a.data;
-    it.B = b.data;
     it.C = c.data;
-    it.n_k = a.n[mi];
-    it.sA_k = a.w[mi];
-    it.n_lo = it.n_hi = 1;
-    int nlo = 0, nhi = 0;
-    for (int i = 0; i < nd; ++i) {
-        if (nlo == 0 && nhi == 0 && (d[i].s[0] < it.sA_k || it.n_k == 1)) {
-            it.n_lo = d[i].n;
-            it.sA_lo = d[i].s[0];
-            it.sC_lo = d[i].s[1];
-            ++nlo;
-        } else {
-            if (nhi) return false;
-            it.n_hi = d[i].n;
-            it.sA_hi = d[i].s[0];
-            it.sC_hi = d[i].s[1];
-            ++nhi;
-        }
-    }
-    if (is_ttm) {
-        it.m = b.n[0];
-        it.sB_j = b.w[0];
-        it.sB_k = b.w[1];
-        it.sC_j = c.w[mi];
+    if (op == 0) {
+        it.kind = BATCH_SCALAR;
+        ndn = coalesce(dn, ndn, 2, 0);  // lanes along A's fastest output dim
+        ndk = coalesce(dk, ndk, 2, 1);
     } else {
-        it.m = 1;
-        it.sB_k = b.w[0];
+        it.kind = BATCH_TILE;
+        if (min_c_stride(dm, ndm) < min_c_stride(dn, ndn)) {
+            // lanes run along N: N takes the group holding C's smallest stride
+            Dim t[MAXP];
+            for (int i = 0; i < ndm; ++i) t[i] = dm[i];
+            for (int i = 0; i < ndn; ++i) dm[i] = dn[i];
+            for (int i = 0; i < ndm; ++i) dn[i] = t[i];
+            std::swap(ndm, ndn);
+            std::swap(X, Y);
+            for (int i = 0; i < ndk; ++i) std::swap(dk[i].s[0], dk[i].s[1]);
+        }
+        ndm = coalesce(dm, ndm, 2, 1);
+        ndn = coalesce(dn, ndn, 2, 1);
+        ndk = coalesce(dk, ndk, 2, 0);
     }
+    if (!fill_grp(it.gm, dm, ndm, 0, 1) || !fill_grp(it.gn, dn, ndn, 0, 1) || !fill_grp(it.gk, dk, ndk, 0, 1))
+        return false;
+    if (it.kind == BATCH_SCALAR && ndk > 1) return false;
+    it.X = X;
+    it.Y = Y;
+    it.M = it.gm.total;
+    it.N = it.gn.total;
+    it.K = it.gk.total;
+    it.tiles_n = (it.N + 63) / 64;
     return true;
 }
+
+static int64_t batch_units(const BatchItem& it) {
+    if (it.kind == BATCH_SCALAR) return (it.N + 255) / 256;
+    return (it.M + 15) / 16 * it.tiles_n;
+}
+
 
 static bool is_perm(int p, const int32_t* v) {
     if (!v && p > 0) return false;
@@ -1304,7 +1461,7 @@ int tlib_ttm(const tlib_tensor* A, const tlib_tensor* B, int32_t m, const tlib_t
     key_ten(key, c);
     Launch last;
     bool settled = false;
-    rc = tuned(key, cands, int(sizeof(cands) / sizeof(cands[0])), s, [&](int pick) {
+    rc = tuned(key, ttm_class_key(a, bm, c, mi), cands, int(sizeof(cands) / sizeof(cands[0])), s, [&](int pick) {
         Launch N;
         int r = plan_ttm(a, bm, mi, c, pick, N);
         if (r != TLIB_OK) return r;
@@ -1490,6 +1647,60 @@ static int plan_ttt(const Ten& a, const Ten& b, int q, const int32_t* phi, const
     return plan_gemm(a.dtype, 0, a.data, b.data, c.data, dm, r, dn, s, dk, q, "ttt", ws_cap, L, tile);
 }
 
+// Outer product (q = 0): C(free A modes in phi order, free B modes in psi
+// order) = A(.) B(.), one product per element, written as a stream along C's
+// unit-stride mode.  Returns PICK_NA when a group does not collapse to at most
+// GMAXD dims or 2^31 indices (the GEMM path then takes it).
+static int plan_outer(const Ten& a, const Ten& b, const int32_t* phi, const int32_t* psi, const Ten& c,
+                      Launch& L) {
+    const int r = a.p, s = b.p;
+    Dim dm[MAXP], dn[MAXP];
+    for (int k = 0; k < r; ++k) dm[k] = {a.n[phi[k] - 1], {a.w[phi[k] - 1], c.w[k], 0}};
+    for (int k = 0; k < s; ++k) dn[k] = {b.n[psi[k] - 1], {b.w[psi[k] - 1], c.w[r + k], 0}};
+    int ndm = coalesce(dm, r, 2, 1), ndn = coalesce(dn, s, 2, 1);
+    int xsrc = 0;
+    auto minc = [](const Dim* d, int nd) {
+        int64_t m = INT64_MAX;
+        for (int i = 0; i < nd; ++i) m = std::min(m, d[i].s[1]);
+        return m;
+    };
+    if (minc(dm, ndm) < minc(dn, ndn)) {  // the group with C's unit stride runs along lanes
+        Dim t[MAXP];
+        for (int i = 0; i < ndm; ++i) t[i] = dm[i];
+        for (int i = 0; i < ndn; ++i) dm[i] = dn[i];
+        for (int i = 0; i < ndm; ++i) dn[i] = t[i];
+        std::swap(ndm, ndn);
+        xsrc = 1;
+    }
+    OuterParams O{};
+    if (!fill_grp(O.gm, dm, ndm, 0, 1) || !fill_grp(O.gn, dn, ndn, 0, 1)) return PICK_NA;
+    O.M = O.gm.total;
+    O.N = O.gn.total;
+    const int v = 16 / esize(acc_dtype(a.dtype));
+    bool vec = ndn >= 1 && dn[0].s[1] == 1 && dn[0].n % v == 0 && (uintptr_t(c.data) % 16) == 0;
+    for (int i = 1; i < ndn; ++i) vec = vec && dn[i].s[1] % v == 0;
+    for (int i = 0; i < ndm; ++i) vec = vec && dm[i].s[1] % v == 0;
+    O.vec = vec ? v : 1;
+    O.nv = O.N / O.vec;
+    int cw = 1, lg = 0;
+    while (cw < 256 && cw < O.nv) {
+        cw *= 2;
+        ++lg;
+    }
+    O.cw = cw;
+    O.cw_log2 = lg;
+    O.rows_per_wg = 256 / cw;
+    plan_note("ttt outer dtype=%s M=%lld N=%lld dims=(%d,%d) vec=%d cw=%d", dname(a.dtype), (long long)O.M,
+              (long long)O.N, ndm, ndn, O.vec, cw);
+    L = Launch();
+    L.kind = LK_OUTER;
+    L.op = "ttt";
+    L.dtype = a.dtype;
+    L.xsrc = xsrc;
+    L.outer = O;
+    return TLIB_OK;
+}
+
 static std::string ttt_pkey(int kind, const Ten& a, const Ten& b, const Ten& c, int q, const int32_t* phi,
                             const int32_t* psi) {
     std::string key;
@@ -1530,6 +1741,17 @@ int tlib_ttt(const tlib_tensor* A, const tlib_tensor* B, int32_t q, const int32_
         g_plan = L->note;
         return exec_launch(*L, a.data, b.data, c.data, ws, st);
     }
+    if (q == 0) {
+        Launch O;
+        if (plan_outer(a, b, phi, psi, c, O) == TLIB_OK) {
+            rc = exec_launch(O, a.data, b.data, c.data, ws, st);
+            if (rc == TLIB_OK) {
+                O.note = g_plan;
+                pc_put(pkey, O);
+            }
+            return rc;
+        }
+    }
     Launch last;
     bool settled = false;
     auto run = [&](int tile) {
@@ -1541,8 +1763,15 @@ int tlib_ttt(const tlib_tensor* A, const tlib_tensor* B, int32_t q, const int32_
         if (r == TLIB_OK) last = std::move(N);
         return r;
     };
-    static const int cands[] = {GT_16x256, GT_64x128, GT_128x128, GT_256x64, GT_64x64, GT_128x64, GT_256x32};
-    rc = tuned(ttt_key(a, b, c, q, phi, psi), cands, int(sizeof(cands) / sizeof(cands[0])), st, run, &settled);
+    // every tile with three split targets (about 1024, 512 and 256 workgroups)
+    static const int cands[] = {GT_16x256, GT_64x128, GT_128x128, GT_256x64, GT_64x64, GT_128x64, GT_256x32,
+                                GT_COUNT + GT_16x256, GT_COUNT + GT_64x128, GT_COUNT + GT_128x128,
+                                GT_COUNT + GT_256x64, GT_COUNT + GT_64x64, GT_COUNT + GT_128x64,
+                                GT_COUNT + GT_256x32, 2 * GT_COUNT + GT_16x256, 2 * GT_COUNT + GT_64x128,
+                                2 * GT_COUNT + GT_128x128, 2 * GT_COUNT + GT_256x64, 2 * GT_COUNT + GT_64x64,
+                                2 * GT_COUNT + GT_128x64, 2 * GT_COUNT + GT_256x32};
+    rc = tuned(ttt_key(a, b, c, q, phi, psi), ttt_class_key(a, b, c, q, phi, psi), cands,
+               int(sizeof(cands) / sizeof(cands[0])), st, run, &settled);
     if (rc == TLIB_OK && settled && last.kind != LK_NONE) {
         last.note = g_plan;
         pc_put(pkey, last);
@@ -1577,8 +1806,10 @@ int tlib_ttt_noalloc(const tlib_tensor* A, const tlib_tensor* B, int32_t q, cons
         return exec_launch(*L, a.data, b.data, c.data, ws, st);
     }
     Launch N;
-    rc = plan_ttt(a, b, q, phi, psi, c, TLIB_NOALLOC_SCRATCH_BYTES, N, -1);
-    if (rc) return rc;
+    if (q != 0 || plan_outer(a, b, phi, psi, c, N) != TLIB_OK) {
+        rc = plan_ttt(a, b, q, phi, psi, c, TLIB_NOALLOC_SCRATCH_BYTES - WS_COUNTER_BYTES, N, -1);
+        if (rc) return rc;
+    }
     rc = exec_launch(N, a.data, b.data, c.data, ws, st);
     if (rc == TLIB_OK) {
         N.note = g_plan;
@@ -1627,6 +1858,36 @@ int tlib_norm(const tlib_tensor* A, double* out_dev, void* stream) {
     if ((rc = normalize(A, a, "A"))) return rc;
     if (!out_dev) return fail(TLIB_EINVAL, "norm: out_dev is NULL");
     return run_dot(a, nullptr, out_dev, true, hipStream_t(stream), "norm");
+}
+
+// u = v / ||v|| with the norm written to norm_dev (Sec. 5.2, the normalisation
+// step of the higher-order power method): the norm kernel, then a division
+// that reads the norm from device memory, so nothing returns to the host.
+int tlib_normalize(const tlib_tensor* A, double* norm_dev, const tlib_tensor* C, void* stream) {
+    begin_call();
+    Ten a, c;
+    int rc;
+    if ((rc = normalize(A, a, "A")) || (rc = normalize(C, c, "C"))) return rc;
+    if (!norm_dev) return fail(TLIB_EINVAL, "normalize: norm_dev is NULL");
+    if (a.p != c.p) return fail(TLIB_ESHAPE, "normalize: orders differ");
+    for (int r = 0; r < a.p; ++r)
+        if (a.n[r] != c.n[r]) return fail(TLIB_ESHAPE, "normalize: extent %d differs", r + 1);
+    if ((rc = check_output(c, "C"))) return rc;
+    const bool in_place = same_view(a, c) && a.dtype == c.dtype;
+    if (!in_place && overlaps(c, a)) return fail(TLIB_EALIAS, "normalize: C overlaps A (only C = A is allowed)");
+    const hipStream_t s = hipStream_t(stream);
+    if ((rc = run_dot(a, nullptr, norm_dev, true, s, "normalize"))) return rc;
+    Dim d[MAXP];
+    for (int r = 0; r < a.p; ++r) d[r] = {a.n[r], {a.w[r], a.w[r], c.w[r]}};
+    const int nd = coalesce(d, a.p, 3, 2);
+    GDims g;
+    fill_gdims(g, d, nd, 3);
+    const std::string dot_plan = g_plan;
+    plan_note("; div dtype=%s->%s total=%lld", dname(a.dtype), dname(c.dtype), (long long)g.total);
+    g_plan = dot_plan + g_plan;
+    if (g_plan_only) return TLIB_OK;
+    rc = launch_div(a.dtype, c.dtype, norm_dev, a.data, c.data, g, s);
+    return rc ? fail(rc, "normalize: launch failed") : TLIB_OK;
 }
 
 static int run_axpby(double alpha, const Ten& a, double beta, const Ten* b, const Ten& c,
@@ -1918,6 +2179,21 @@ size_t tlib_batch_table_bytes(int32_t n) {
     return sizeof(BatchHeader) + size_t(n < 0 ? 0 : n) * sizeof(BatchItem);
 }
 
+// Validate one grouped request and collapse it (rc TLIB_ESTRIDE: valid, but
+// not for the grouped kernel).
+static int batch_request(const tlib_request& r, BatchItem& it) {
+    Ten a, b, c;
+    int rc;
+    if (r.op == 0) rc = check_ttv(r.A, r.B, r.mode, r.C, a, b, c);
+    else if (r.op == 1) rc = check_ttm(r.A, r.B, r.mode, r.C, a, b, c);
+    else if (r.op == 2) rc = check_ttt(r.A, r.B, r.q, r.phi, r.psi, r.C, a, b, c);
+    else return fail(TLIB_EINVAL, "batch: unknown op %d", r.op);
+    if (rc) return rc;
+    if (!batch_item(r.op, a, b, c, r.mode - 1, r.q, r.phi, r.psi, it))
+        return fail(TLIB_ESTRIDE, "batch: a request does not collapse to the grouped kernel's index groups");
+    return TLIB_OK;
+}
+
 int tlib_batch_plan(const tlib_request* reqs, int32_t n, void* table_host, size_t table_bytes,
                     int64_t* units, int32_t* bad) {
     begin_call();
@@ -1928,30 +2204,31 @@ int tlib_batch_plan(const tlib_request* reqs, int32_t n, void* table_host, size_
     BatchItem* items = (BatchItem*)((char*)table_host + sizeof(BatchHeader));
     int64_t total = 0;
     for (int i = 0; i < n; ++i) {
-        Ten a, b, c;
-        const bool is_ttm = reqs[i].op == 1;
-        if (reqs[i].op != 0 && reqs[i].op != 1) {
-            if (bad) *bad = i;
-            return fail(TLIB_EINVAL, "batch: request %d has unknown op %d", i, reqs[i].op);
-        }
-        int rc = is_ttm ? check_ttm(reqs[i].A, reqs[i].B, reqs[i].mode, reqs[i].C, a, b, c)
-                        : check_ttv(reqs[i].A, reqs[i].B, reqs[i].mode, reqs[i].C, a, b, c);
+        const int rc = batch_request(reqs[i], items[i]);
         if (rc) {
             if (bad) *bad = i;
             return rc;
         }
-        if (!batch_item(a, b, reqs[i].mode - 1, c, is_ttm, items[i])) {
-            if (bad) *bad = i;
-            return fail(TLIB_ESTRIDE, "batch: request %d does not collapse to one (lo, k, hi) form", i);
-        }
         items[i].unit_begin = total;
-        total += (items[i].n_lo * items[i].m * items[i].n_hi + 255) / 256;
+        total += batch_units(items[i]);
     }
     hdr->n_items = n;
     hdr->total_units = total;
     if (units) *units = total;
     plan_note("batch items=%d units=%lld", n, (long long)total);
     return TLIB_OK;
+}
+
+int tlib_request_groupable(const tlib_request* r) {
+    begin_call();
+    if (!r || !r->C) return 0;
+    // a result the server places later is checked at a stand-in address
+    tlib_tensor c = *r->C;
+    if (!c.data) c.data = reinterpret_cast<void*>(uintptr_t(4096));
+    tlib_request q = *r;
+    q.C = &c;
+    BatchItem it;
+    return batch_request(q, it) == TLIB_OK ? 1 : 0;
 }
 
 int tlib_batch_run(const void* table_dev, int32_t grid, void* stream) {
@@ -1990,11 +2267,9 @@ int tlib_workspace_reserve(void* stream, size_t bytes) {
     std::lock_guard<std::mutex> lk(g_ws_mu);
     WsBuf& e = g_ws[{dev, s}];
     if (e.ptr && e.bytes >= bytes) return TLIB_OK;
-    void* p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(TLIB_ENOMEM, "workspace_reserve: hipMalloc of %zu bytes failed", bytes);
-    }
+    bytes += WS_COUNTER_BYTES;
+    void* p = ws_alloc(bytes, s);
+    if (!p) return fail(TLIB_ENOMEM, "workspace_reserve: allocation of %zu bytes failed", bytes);
     if (e.ptr) e.retired.push_back(e.ptr);  // graphs captured earlier may still use it
     e.ptr = static_cast<char*>(p);
     e.bytes = bytes;

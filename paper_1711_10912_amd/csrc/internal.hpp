@@ -115,6 +115,8 @@ struct GemmParams {
     int32_t y_vec;           // > 0: Y loaded as vectors of y_vec elements along N (K one dim, stride syk)
     int64_t syk;
     int32_t kvec;            // bit 0 / bit 1: X / Y loaded as groups of consecutive k (8 for 16-bit, 2 for FP32/FP64)
+    int32_t* cnt;            // split-K: per-tile arrival counters (zero on entry, left zero); null = sum in a
+                             // second kernel
 };
 
 // Multi-mode TTV (one pass over A).  A group of modes in storage order,
@@ -214,6 +216,21 @@ struct TtmRowParams {
     int32_t nrg;  // row groups, ceil(M / mr); the grid is a multiple of 8 * nrg when nrg > 1
 };
 
+// Outer product (k_outer.hip): C[m, n] = X[m] * Y[n]; gm: s0 = X stride, s1 =
+// C stride; gn: s0 = Y stride, s1 = C stride (N holds C's unit-stride mode).
+// Columns go in vectors of `vec` (16-byte stores) or singly; a workgroup
+// chunk holds cw (a power of two <= 256) column vectors and takes
+// rows_per_wg = 256 / cw rows at a time.
+struct OuterParams {
+    const void* X;
+    const void* Y;
+    void* C;
+    int64_t M, N, nv;
+    Grp gm, gn;
+    int32_t vec, cw, cw_log2, rows_per_wg;
+};
+int launch_outer(int dtype, const OuterParams& p, hipStream_t s);
+
 // Work table of a grouped launch (k_batch.hip): a header followed by items.
 struct BatchHeader {
     int32_t n_items;
@@ -221,15 +238,21 @@ struct BatchHeader {
     int64_t total_units;  // units of 256 outputs over all items
     int64_t pad1[2];
 };
+// Item kinds: BATCH_SCALAR = one thread per output (M = 1, K one dim),
+// BATCH_TILE = 16 x 64 tiles of C on matrix cores.
+enum { BATCH_SCALAR = 0, BATCH_TILE = 1 };
+// One request as C[m, n] = sum_k X[m, k] Y[k, n]; gm: s0 = X, s1 = C;
+// gn: s0 = Y, s1 = C; gk: s0 = X, s1 = Y.
 struct BatchItem {
     int32_t dtype;  // input dtype; C is FP64 for FP64 input, FP32 otherwise
-    int32_t pad0;
+    int32_t kind;
     int64_t unit_begin;  // first unit of this item (prefix sum)
-    const void* A;
-    const void* B;
+    const void* X;
+    const void* Y;
     void* C;
-    int64_t n_lo, n_k, n_hi, m;  // TTV: m = 1
-    int64_t sA_lo, sA_k, sA_hi, sB_j, sB_k, sC_lo, sC_j, sC_hi;
+    int64_t M, N, K;
+    int64_t tiles_n;  // BATCH_TILE: ceil(N / 64)
+    Grp gm, gn, gk;
 };
 int launch_batch(const void* table_dev, int grid, hipStream_t s);
 
@@ -254,6 +277,7 @@ int launch_ttv_generic(int dtype, const TtvParams& p, const GDims& out, hipStrea
 int launch_ttv_fiber(int dtype, const TtvParams& p, const Grp& go, int G, hipStream_t s);
 
 int launch_gemm(int dtype, int tile, const GemmParams& p, hipStream_t s);
+int gemm_slice_k(int dtype, int tile);  // K depth of one LDS slice of the tile
 // prep + main + finish kernels of the one-pass multi-mode TTV; vec: 16-byte loads
 int launch_tv(int dtype, const TvParams& P, void* c, int64_t cs, bool vec, hipStream_t s);
 int launch_ttm2(int dtype, const Ttm2Params& P, bool vec, hipStream_t s);
@@ -277,6 +301,9 @@ int launch_dot(int dtype, const void* A, const void* B, const GDims& d, double* 
                void* ws, size_t ws_bytes, hipStream_t s);
 int dot_partials(int64_t total);  // number of first-pass partials for a given size
 
+// C = A / den[0] (den in device memory) over GDims (strides s[0] = A, s[2] = C).
+int launch_div(int in_dtype, int out_dtype, const double* den, const void* A, void* C, const GDims& g,
+               hipStream_t s);
 // C = alpha*A + beta*B over GDims (strides s[0]=A, s[1]=B, s[2]=C); B may be null.
 // A and B have in_dtype; C has out_dtype (correctly rounded from FP64).
 int launch_axpby(int in_dtype, int out_dtype, double alpha, const void* A, double beta, const void* B,
@@ -291,6 +318,10 @@ int launch_axpby_tile(int in_dtype, int out_dtype, double alpha, const void* A, 
 // or a fixed buffer the caller brings (`fixed`).  take() hands out 256-byte
 // aligned pieces from the start and returns nullptr when the buffer cannot
 // hold them (or cannot be allocated); it never frees or waits.
+// The last WS_COUNTER_BYTES of every buffer hold per-tile counters of the
+// split-K GEMM (zero when the buffer is created; each kernel that uses one
+// sets it back to zero), so they are not handed out by take().
+constexpr size_t WS_COUNTER_BYTES = size_t(64) << 10;
 struct WsCtx {
     hipStream_t s = nullptr;
     char* base = nullptr;
@@ -300,7 +331,9 @@ struct WsCtx {
     bool fixed = false;
     void* take(size_t bytes);
     void need(size_t bytes);
-    size_t avail() const { return size > used ? size - used : 0; }
+    size_t avail_total() const { return size > WS_COUNTER_BYTES ? size - WS_COUNTER_BYTES : 0; }
+    size_t avail() const { return avail_total() > used ? avail_total() - used : 0; }
+    int32_t* counters() const { return reinterpret_cast<int32_t*>(base + size - WS_COUNTER_BYTES); }
 };
 
 }  // namespace tlib

@@ -50,12 +50,19 @@ template <> struct Mfma<float> {
 template <> struct Mfma<bf16_t> {
     using acc_t = f4_t;
     static constexpr int KSTEP = 32;
-    static constexpr int BK = 32;
+    static constexpr int BK = 128;
 };
 template <> struct Mfma<f16_t> {
     using acc_t = f4_t;
     static constexpr int KSTEP = 32;
-    static constexpr int BK = 32;
+    static constexpr int BK = 128;
+};
+
+// K slice depth of a tile: 16-bit slices hold four MFMA k-steps (two for
+// tiles with BM + BN > 256, whose 128-deep slices would leave room for only
+// one workgroup per CU).
+template <typename TI, int BM, int BN> struct SliceK {
+    static constexpr int value = sizeof(TI) == 2 && BM + BN > 256 ? 64 : Mfma<TI>::BK;
 };
 
 __device__ __forceinline__ d4_t mfma_step(double a, double b, d4_t c) {
@@ -98,7 +105,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
     using RT = typename Raw<TI>::type;
     using acc_t = typename Mfma<TI>::acc_t;
     constexpr bool WIDE = sizeof(TI) == 2;
-    constexpr int BK = Mfma<TI>::BK;
+    constexpr int BK = SliceK<TI, BM, BN>::value;
     constexpr int KSTEP = Mfma<TI>::KSTEP;
     constexpr int WM = BM / WGM, WN = BN / WGN;
     constexpr int FM = WM / 16, FN = WN / 16;
@@ -116,7 +123,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
     // YW & 16 / YW & 32 = X / Y loaded as groups of 2 consecutive k.  16-bit:
     // YW bit 0 / bit 1 = X / Y loaded as 16-byte groups of 8 consecutive k
     // (see fetch).
-    constexpr bool YV = !WIDE && (YW & 15) > 0;
+    constexpr bool YV = WIDE ? (YW & 4) != 0 : (YW & 15) > 0;
     constexpr bool XKV = WIDE ? (YW & 1) != 0 : (YW & 16) != 0;
     constexpr bool YKV = WIDE ? (YW & 2) != 0 : (YW & 32) != 0;
     constexpr int GVX = WIDE ? 8 : 2;              // k per X / Y group
@@ -125,12 +132,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
     constexpr int NXV = BM * KGX, NYV = BN * KG;   // k groups per X / Y slice
     constexpr int EXV = (NXV + 255) / 256, EYK = (NYV + 255) / 256;
     using xg_t = typename std::conditional<(WIDE || sizeof(TI) == 8), u4_t, u2_t>::type;
-    constexpr int VY = YV ? (YW & 15) : 1;
+    constexpr int VY = YV ? (WIDE ? 8 : (YW & 15)) : 1;
     constexpr int CG = BN / VY;                   // column groups of a Y slice
     constexpr int RS = YV ? 256 / CG : 1;         // rows of the slice per pass
     constexpr int EYV = YV ? BK / RS : 1;         // vectors per thread per slice
-    static_assert(!YV || (sizeof(TI) >= 4 && 256 % CG == 0 && BK % RS == 0 && EYV >= 1), "vector Y slice");
-    using YE = typename std::conditional<(sizeof(TI) >= 4), TI, float>::type;
+    static_assert(!YV || (256 % CG == 0 && BK % RS == 0 && EYV >= 1), "vector Y slice");
+    using YE = typename std::conditional<(sizeof(TI) >= 4), TI, uint16_t>::type;
     typedef YE yv_t __attribute__((ext_vector_type(VY)));
 
     // The X/Y slices and, after the K loop, the epilogue's staging rows share
@@ -266,7 +273,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
 #pragma unroll
                     for (int e = 0; e < VY; ++e) {
                         const int64_t a = ycol[ycg * VY + e];
-                        yvr[j][e] = *((a >= 0 && k < kend) ? Y + (a + int64_t(k) * P.syk) : zsrc);
+                        yvr[j][e] = raw_load((a >= 0 && k < kend) ? Y + (a + int64_t(k) * P.syk) : zsrc);
                     }
                 }
             }
@@ -324,8 +331,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
                 }
             }
         } else if constexpr (YV) {
+            if constexpr (WIDE) {
+                // the slice is stored n-major (k contiguous per column, as the
+                // 16-bit MFMA operands read it): each vector's eight columns
+                // go to eight rows
 #pragma unroll
-            for (int j = 0; j < EYV; ++j) *reinterpret_cast<yv_t*>(&Ys[(yrow + RS * j) * PY + ycg * VY]) = yvr[j];
+                for (int j = 0; j < EYV; ++j)
+#pragma unroll
+                    for (int e = 0; e < VY; ++e) Ys[(ycg * VY + e) * PY + yrow + RS * j] = yvr[j][e];
+            } else {
+#pragma unroll
+                for (int j = 0; j < EYV; ++j)
+                    *reinterpret_cast<yv_t*>(&Ys[(yrow + RS * j) * PY + ycg * VY]) = yvr[j];
+            }
         } else {
 #pragma unroll
             for (int j = 0; j < EY; ++j) {
@@ -407,7 +425,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
     constexpr int RQ = std::is_same<TI, double>::value ? 1 : 4;
     constexpr int RR = std::is_same<TI, double>::value ? 4 : 1;
     if (P.ksplit > 1) {
-        TA* part = (TA*)P.part + int64_t(kz) * P.M * P.N;
+        const int64_t MN = int64_t(P.M) * P.N;
+        TA* part = (TA*)P.part + int64_t(kz) * MN;
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
             const int col = n0 + wn0 + j * 16 + rl;
@@ -420,6 +439,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
                     if (row < P.M) part[int64_t(row) * P.N + col] = acc[i][j][r];
                 }
         }
+        if (!P.cnt) return;  // gemm_ksum_kernel sums the partials
+        // The slice of this tile that finishes last sums all slices' partials
+        // in slice order (the order of gemm_ksum_kernel) and writes C, then
+        // sets the tile's counter back to zero for the next call.  The fences
+        // make the partials visible across the device (other XCDs' L2s)
+        // before the count, and the count before they are read.
+        __shared__ int s_last;
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) s_last = atomicAdd(&P.cnt[bid], 1) == P.ksplit - 1;
+        __syncthreads();
+        if (!s_last) return;
+        __threadfence();
+        const TA* pp = (const TA*)P.part;
+        TA* C = (TA*)P.C;
+        for (int e = tid; e < BM * BN; e += 256) {
+            const int r = e / BN, c = e - (e / BN) * BN;
+            const int row = m0 + r, col = n0 + c;
+            if (row >= P.M || col >= P.N) continue;
+            const int64_t o = int64_t(row) * P.N + col;
+            TA sum = __builtin_nontemporal_load(pp + o);
+            for (int z = 1; z < P.ksplit; ++z) sum += __builtin_nontemporal_load(pp + int64_t(z) * MN + o);
+            C[crow[r] + ccol[c]] = sum;
+        }
+        if (tid == 0) P.cnt[bid] = 0;
         return;
     }
     // Staged epilogue: each wave writes one 16-row block of its tile to LDS,
@@ -528,16 +572,19 @@ static int gemm_launch(const GemmParams& p, hipStream_t s) {
             else TLIB_GEMM(0);
         }
     } else {
-        switch (p.kvec) {
+        // bit 0 / 1: X / Y in k groups; bit 2: Y as 8-element vectors along N
+        switch ((p.kvec & 3) | (p.y_vec ? 4 : 0)) {
             case 1: hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 1>), grid, dim3(256), 0, s, p); break;
             case 2: hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 2>), grid, dim3(256), 0, s, p); break;
             case 3: hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 3>), grid, dim3(256), 0, s, p); break;
+            case 4: hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 4>), grid, dim3(256), 0, s, p); break;
+            case 5: hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 5>), grid, dim3(256), 0, s, p); break;
             default: hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, WGM, WGN, 0>), grid, dim3(256), 0, s, p);
         }
     }
 #undef TLIB_GEMM
     if (hipGetLastError() != hipSuccess) return TLIB_EHIP;
-    if (p.ksplit > 1) {
+    if (p.ksplit > 1 && !p.cnt) {
         const int64_t MN = int64_t(p.M) * p.N;
         const unsigned g = unsigned(std::min<int64_t>((MN + 255) / 256, 65536));
         hipLaunchKernelGGL((gemm_ksum_kernel<TA>), dim3(g), dim3(256), 0, s, p);
@@ -558,6 +605,29 @@ static int gemm_dispatch(int tile, const GemmParams& p, hipStream_t s) {
         case GT_256x32: return gemm_launch<TI, 256, 32, 4, 1>(p, s);
     }
     return TLIB_EINVAL;
+}
+
+template <typename TI>
+static int slice_k(int tile) {
+    switch (tile) {
+        case GT_16x256: return SliceK<TI, 16, 256>::value;
+        case GT_64x128: return SliceK<TI, 64, 128>::value;
+        case GT_128x128: return SliceK<TI, 128, 128>::value;
+        case GT_256x64: return SliceK<TI, 256, 64>::value;
+        case GT_64x64: return SliceK<TI, 64, 64>::value;
+        case GT_128x64: return SliceK<TI, 128, 64>::value;
+        case GT_256x32: return SliceK<TI, 256, 32>::value;
+    }
+    return Mfma<TI>::BK;
+}
+
+int gemm_slice_k(int dtype, int tile) {
+    switch (dtype) {
+        case TLIB_F64: return slice_k<double>(tile);
+        case TLIB_F32: return slice_k<float>(tile);
+        case TLIB_BF16: return slice_k<bf16_t>(tile);
+        default: return slice_k<f16_t>(tile);
+    }
 }
 
 int launch_gemm(int dtype, int tile, const GemmParams& p, hipStream_t s) {

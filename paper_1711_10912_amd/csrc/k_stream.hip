@@ -310,6 +310,51 @@ int launch_axpby(int in_dtype, int out_dtype, double alpha, const void* A, doubl
     return TLIB_EDTYPE;
 }
 
+// C = A / den[0] with den in device memory (the normalisation step of the
+// higher-order power method after the norm kernel wrote den): the quotient
+// is formed in FP64 and rounded once to C's type.
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void div_kernel(const double* den, const TI* A, TO* C, GDims g) {
+    const double d = den[0];
+    const bool flat = g.nd <= 1 && g.s[0][0] == 1 && g.s[2][0] == 1;
+    const int64_t stride = int64_t(gridDim.x) * 256;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < g.total; i += stride) {
+        int64_t off[3];
+        if (flat) off[0] = off[1] = off[2] = i;
+        else gd_decode(i, g, 3, off);
+        C[off[2]] = round_out<TO>(to_f64(A[off[0]]) / d);
+    }
+}
+
+template <typename TI, typename TO>
+static int div_launch(const double* den, const void* A, void* C, const GDims& g, hipStream_t s) {
+    const unsigned blocks = unsigned(std::max<int64_t>(1, std::min<int64_t>((g.total + 255) / 256, 8192)));
+    hipLaunchKernelGGL((div_kernel<TI, TO>), dim3(blocks), dim3(256), 0, s, den, (const TI*)A, (TO*)C, g);
+    return hipGetLastError() == hipSuccess ? TLIB_OK : TLIB_EHIP;
+}
+
+template <typename TI>
+static int div_out(int out_dtype, const double* den, const void* A, void* C, const GDims& g, hipStream_t s) {
+    switch (out_dtype) {
+        case TLIB_F64: return div_launch<TI, double>(den, A, C, g, s);
+        case TLIB_F32: return div_launch<TI, float>(den, A, C, g, s);
+        case TLIB_BF16: return div_launch<TI, bf16_t>(den, A, C, g, s);
+        case TLIB_F16: return div_launch<TI, f16_t>(den, A, C, g, s);
+    }
+    return TLIB_EDTYPE;
+}
+
+int launch_div(int in_dtype, int out_dtype, const double* den, const void* A, void* C, const GDims& g,
+               hipStream_t s) {
+    switch (in_dtype) {
+        case TLIB_F64: return div_out<double>(out_dtype, den, A, C, g, s);
+        case TLIB_F32: return div_out<float>(out_dtype, den, A, C, g, s);
+        case TLIB_BF16: return div_out<bf16_t>(out_dtype, den, A, C, g, s);
+        case TLIB_F16: return div_out<f16_t>(out_dtype, den, A, C, g, s);
+    }
+    return TLIB_EDTYPE;
+}
+
 // ------------------------------------------------------------------ tiled relayout
 // The same entrywise op when C's fastest dimension x is not A's fastest y
 // (a transpose, or add/scale into another layout).  A block owns a 32 x 32

@@ -4,7 +4,7 @@
 // A scheduler thread owns S HIP streams ("slots").  Requests are admitted in
 // arrival order while a slot is free and their output fits in the output
 // arena (the HBM budget for results), so requests that arrive while others
-// run start as soon as memory and slots free up.  Consecutive small TTV/TTM
+// run start as soon as memory and slots free up.  Consecutive small TTV/TTM/TTT
 // requests are fused into one grouped launch: the batch is planned into a
 // pinned host table, copied to the slot's device table and run by a graph
 // captured once per slot.  Every other request runs through the regular entry
@@ -60,6 +60,9 @@ struct Job {
     bool grouped = false;
     double t_arrival = 0, t_done = 0;
     int err = 0;
+    tlib_request request() {
+        return tlib_request{op, mode, &a.t, &b.t, &c.t, q, 0, op == 2 ? phi : nullptr, op == 2 ? psi : nullptr};
+    }
 };
 
 // First-fit allocator over [0, size) with 256-byte granularity.
@@ -193,7 +196,7 @@ struct tlib_server {
         std::vector<tlib_request> req(jobs.size());
         for (size_t i = 0; i < jobs.size(); ++i) {
             place_output(jobs[i]);
-            req[i] = tlib_request{jobs[i]->op, jobs[i]->mode, &jobs[i]->a.t, &jobs[i]->b.t, &jobs[i]->c.t};
+            req[i] = jobs[i]->request();
         }
         int64_t units = 0;
         int32_t bad = -1;
@@ -357,9 +360,16 @@ int tlib_server_submit(tlib_server* S, int32_t op, const tlib_tensor* A, const t
     const int esz = C->dtype == TLIB_F64 ? 8 : C->dtype == TLIB_F32 ? 4 : 2;
     j->out_bytes = size_t(span + 1) * size_t(esz);
     int64_t macs = outs;
-    if (op == 0) macs = outs * j->a.n[mode - 1];
-    else if (op == 1) macs = outs * j->a.n[mode - 1];
-    j->grouped = op != 2 && macs <= S->group_macs;
+    if (op == 0 || op == 1) {
+        macs = outs * j->a.n[mode - 1];
+    } else {
+        for (int k = A->order - q; k < A->order; ++k) macs *= j->a.n[phi[k] - 1];
+    }
+    // grouping depends on the request alone, so it runs the same way in any mix
+    if (macs <= S->group_macs) {
+        const tlib_request rq = j->request();
+        j->grouped = tlib_request_groupable(&rq) == 1;
+    }
     j->t_arrival = t;
     {
         std::lock_guard<std::mutex> lk(S->mu);

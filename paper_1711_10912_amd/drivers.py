@@ -10,17 +10,20 @@ def hopm(A, us: Sequence, iters: int) -> Tuple[List[float], list]:
     """Higher-order power method (Sec. 5.2): for each of `iters` sweeps and each
     mode r, u_r <- A times every u_k (k != r, highest mode first);
     lambda_r <- ||u_r|| (FP64); u_r <- u_r / lambda_r.  `us` are device vectors
-    of A's dtype.  Returns (lambdas, us) with lambdas as host floats."""
-    from . import norm, scale, times_vectors
+    of A's dtype.  The norms and the division stay on the device
+    (tlib_normalize); the lambdas of the last sweep are read back once at the
+    end.  Returns (lambdas as host floats, us)."""
+    import torch
+
+    from . import normalize, times_vectors
 
     us = [u.clone() for u in us]
-    lam = [0.0] * A.dim()
+    lam = torch.zeros(A.dim(), dtype=torch.float64, device=A.device)
     for _ in range(iters):
         for r in range(A.dim()):
             v = times_vectors(A, us, r + 1)
-            lam[r] = float(norm(v).item())
-            us[r] = scale(1.0 / lam[r], v, dtype=A.dtype)
-    return lam, us
+            normalize(v, out=us[r], norm_out=lam[r])
+    return [float(x) for x in lam.cpu()], us
 
 
 def tucker(A, Us: Sequence, stage_dtype=None):

@@ -4,7 +4,7 @@ Requests (TTV, TTM, TTT of uneven order and shape, each in its own dtype)
 are submitted as they arrive and refer to operands that stay resident on the
 device.  The library's scheduler thread admits them in arrival order while a
 stream slot is free and the result fits in the output arena (the HBM budget
-for results), fuses consecutive small TTV/TTM requests into one grouped launch
+for results), fuses consecutive small TTV/TTM/TTT requests into one grouped launch
 replayed from a per-slot HIP graph, and times completions with GPU events.
 This module only builds descriptors and forwards calls.
 """
@@ -64,16 +64,22 @@ class Server:
         code = T._dtype_code(acc)
         return None, _lib.desc(0, code, shape, None, lay)
 
-    def submit(self, op: str, a, b, mode: int = 0, q: int = 0, phi=(), psi=()) -> int:
+    def submit(self, op: str, a, b, mode: int = 0, q: int = 0, phi=(), psi=(), out=None) -> int:
+        """Queue one request; `out` (a device tensor of the result's shape and
+        dtype) makes the result caller-owned instead of placed by the server."""
         da, db = self._desc(a), self._desc(b)
-        out, dc = self._out_desc(op, a, b, mode, q, phi, psi)
+        if out is not None:
+            import paper_1711_10912_amd as T
+            dc = T._desc(out)
+        else:
+            out, dc = self._out_desc(op, a, b, mode, q, phi, psi)
         rid = ctypes.c_int64(-1)
         pa = _lib.i32_array(phi) if op == "ttt" else None
         pb = _lib.i32_array(psi) if op == "ttt" else None
         rc = self.L.tlib_server_submit(self.h, _OPS[op], ctypes.byref(da), ctypes.byref(db), int(mode), int(q),
                                        pa, pb, ctypes.byref(dc), ctypes.byref(rid))
         _lib.check(rc)
-        if out is not None:
+        if out is not None and self.keep:
             self.outputs[rid.value] = out
         return rid.value
 

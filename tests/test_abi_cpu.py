@@ -167,7 +167,7 @@ def test_ttt_noalloc_bounds_its_split_by_the_static_scratch():
     """tlib_ttt_noalloc plans the same contraction as tlib_ttt (Sec. 5.2
     Eq. ttt) with its split-K slices bounded by the static scratch size."""
     L = _lib.lib()
-    cap = 16 << 20
+    cap = (16 << 20) - (64 << 10)  # the scratch less its split-K counters
     with Plan():
         for (na, nb, nc, dt, es) in (((96, 80, 64, 48), (64, 48, 120), (96, 80, 120), _lib.F32, 4),  # 3.7 MB a slice
                                      ((8, 4, 4096), (4, 4096, 8), (8, 8), _lib.F32, 4),  # tiny M N, deep K
@@ -289,6 +289,67 @@ def test_autotune_controls(tmp_path):
     finally:
         T.autotune_clear()
         T.set_autotune(prev)
+
+
+def test_autotune_class_entries_serve_unseen_shapes(tmp_path):
+    """A table entry keyed by shape class (dtype, layout flags, base-4 size
+    buckets) serves shapes that have no exact entry; an exact entry wins over
+    its class's (plan-only calls in frozen mode never tune)."""
+    import paper_1711_10912_amd as T
+    prev = T.set_autotune("frozen")
+    try:
+        T.autotune_clear()
+        tab = tmp_path / "cls.txt"
+        # TTM FP32, mode 2 not unit-stride, C not contiguous along j, n_m 90
+        # (bucket 3), 64 rows (3), 8100 columns (6), n_lo 90 (3): GEMM tile 128x128
+        # (pick 2 + tile 2); TTT FP32 with A and B k-fast, C's unit stride in
+        # free A, M 7680 (6), N 120 (3), K 3072 (5): tile 256x32 (pick 6)
+        tab.write_text("4 class:ttm|1|0|0|3|3|6|3\n6 class:ttt|1|1|1|1|6|3|5\n")
+        T.autotune_load(str(tab))
+        with Plan():
+            for n in (90, 100):  # both shapes fall in the class
+                A = _d((n, 90, n), _lib.F32)
+                B = _d((64, 90), _lib.F32, ptr=FAKE * 2)
+                C = _d((n, 64, n), _lib.F32, ptr=FAKE * 3)
+                assert _ttm(A, B, 2, C) == 0
+                p = _plan()
+                assert "tile=128x128" in p and "autotuned(class)" in p, p
+            Ad = _d((96, 80, 64, 48), _lib.F32, layout=(4, 3, 2, 1))
+            Bd = _d((64, 48, 120), _lib.F32, ptr=FAKE * 2)
+            Cd = _d((96, 80, 120), _lib.F32, ptr=FAKE * 3)
+            L = _lib.lib()
+            phi, psi = _lib.i32_array((1, 2, 3, 4)), _lib.i32_array((3, 1, 2))
+            assert L.tlib_ttt(ctypes.byref(Ad), ctypes.byref(Bd), 2, phi, psi, ctypes.byref(Cd), None) == 0
+            p = _plan()
+            assert "tile=256x32" in p and "autotuned(class)" in p, p
+            # a shape of another class takes the planner's rule
+            A = _d((90, 90, 90), _lib.F32, layout=(3, 2, 1))
+            B = _d((64, 90), _lib.F32, ptr=FAKE * 2)
+            C = _d((64, 90, 90), _lib.F32, ptr=FAKE * 3, layout=(3, 2, 1))
+            assert _ttm(A, B, 1, C) == 0
+            assert "autotuned" not in _plan()
+    finally:
+        T.autotune_clear()
+        T.set_autotune(prev)
+
+
+def test_normalize_plan_and_errors():
+    """tlib_normalize: a norm (dot kernel) then the division; shapes checked,
+    in place allowed only on the very same view."""
+    L = _lib.lib()
+    with Plan():
+        A = _d((7, 11, 13), _lib.F32)
+        C = _d((7, 11, 13), _lib.BF16, ptr=FAKE * 2, layout=(3, 2, 1))
+        nrm = ctypes.c_void_p(FAKE * 3)
+        assert L.tlib_normalize(ctypes.byref(A), nrm, ctypes.byref(C), None) == 0
+        p = _plan()
+        assert "normalize dot" in p and "div dtype=f32->bf16 total=1001" in p, p
+        assert L.tlib_normalize(ctypes.byref(A), nrm, ctypes.byref(A), None) == 0
+        assert L.tlib_normalize(ctypes.byref(A), None, ctypes.byref(C), None) == _lib.EINVAL
+        assert L.tlib_normalize(ctypes.byref(A), nrm, ctypes.byref(_d((7, 11, 12), _lib.F32, ptr=FAKE * 2)),
+                                None) == _lib.ESHAPE
+        A2 = _d((7, 11, 13), _lib.F32, layout=(2, 1, 3))  # same buffer, other strides
+        assert L.tlib_normalize(ctypes.byref(A), nrm, ctypes.byref(A2), None) == _lib.EALIAS
 
 
 def _tv(A, us, r, c):

@@ -1,6 +1,7 @@
 """GPU parity of the composite drivers (HOPM, Tucker chain), of the fused
 conversion in scale, against the oracle's drivers on the same inputs."""
 import math
+import zlib
 
 import numpy as np
 import pytest
@@ -95,3 +96,36 @@ def test_scale_converts_with_one_rounding(T, src, dst):
     C = T.scale(1.5, A, layout=[1, 2, 3], dtype=torch_dtype(dst))
     want = correctly_rounded(1.5 * round_to(X, src), dst)
     assert np.array_equal(to_np(C), want)
+
+
+@pytest.mark.parametrize("din,dout", [("f64", "f64"), ("f32", "f32"), ("f32", "bf16"), ("bf16", "bf16"),
+                                      ("f16", "f32")])
+def test_normalize_vs_oracle(T, din, dout):
+    """tlib_normalize (the HOPM normalisation, Sec. 5.2): the FP64 norm
+    against the oracle's Neumaier-summed inner product, and every quotient
+    equal to the FP64 quotient by that norm rounded once to C's dtype, for a
+    vector, a strided vector, a 3-way tensor in another layout and in place."""
+    import torch
+    from _util import correctly_rounded, round_to, torch_dtype
+    g = synth.rng(60, zlib.crc32((din + dout).encode()) % 1000)
+    for shape, lay, step in [((160,), None, 1), ((300,), None, 3), ((7, 11, 13), [3, 1, 2], 1)]:
+        X = synth.uniform(shape, g) * 10
+        if step > 1:
+            big = T.empty((shape[0] * step,), None, torch_dtype(din), "cuda")
+            big.copy_(torch.from_numpy(np.repeat(X, step)).to(torch_dtype(din)).cuda())
+            A = big[::step]
+        else:
+            A = to_gpu(X, lay, din)
+        Xr = to_np(A)
+        out = T.empty(shape, None, torch_dtype(dout), "cuda").fill_(float("nan"))
+        _, nrm = T.normalize(A, out=out)
+        torch.cuda.synchronize()
+        nref = math.sqrt(oracle.inner(oracle.materialize(Xr), oracle.materialize(Xr)))
+        n = float(nrm.item())
+        assert abs(n - nref) <= 1e-13 * nref, (n, nref)
+        assert np.array_equal(to_np(out), correctly_rounded(Xr / n, dout))
+        if din == dout and step == 1:
+            B = A.clone()
+            T.normalize(B, out=B)
+            torch.cuda.synchronize()
+            assert np.array_equal(to_np(B), correctly_rounded(Xr / n, dout))

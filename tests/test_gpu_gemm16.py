@@ -111,3 +111,77 @@ def test_ttt_fullsize_with_table(T, alay):
     finally:
         T.autotune_clear()
         T.set_autotune(prev)
+
+
+
+def _yvec(plan):
+    return int(plan.split("yvec=")[1].split()[0])
+
+
+def _ten_key(t):
+    from paper_1711_10912_amd import _lib
+    code = {"torch.float64": _lib.F64, "torch.float32": _lib.F32, "torch.bfloat16": _lib.BF16,
+            "torch.float16": _lib.F16}[str(t.dtype)]
+    return "|%d:%d" % (code, t.dim()) + "".join(",%d/%d" % (n, w) for n, w in zip(t.shape, t.stride()))
+
+
+def _force_ttt_tile(T, tmp_path, A, B, C, q, phi, psi, tile):
+    """A one-entry kernel table that picks `tile` for this exact call shape."""
+    key = "ttt|%d" % q + "".join("|%d" % v for v in phi) + "".join("|%d" % v for v in psi)
+    key += _ten_key(A) + _ten_key(B) + _ten_key(C)
+    f = tmp_path / "tile.txt"
+    f.write_text("%d %s\n" % (tile, key))
+    T.autotune_clear()
+    T.autotune_load(str(f))
+
+
+TILES = ["16x256", "64x128", "128x128", "256x64", "64x64", "128x64", "256x32"]
+
+
+# (free A extents, contracted extents, free B extents, vectors expected)
+# A's first mode may be a view of a longer one (pad): columns then run in
+# pieces of that extent, spaced by the padded length.
+VEC_CASES = [((40,), (24, 40), (3,), 0, True),          # N = 40 ragged against every tile
+             ((12, 6), (64, 48), (5,), 16, True),       # runs of 12 columns 16 apart: some waves load singly
+             ((37,), (24, 40), (2, 3), 0, False)]       # K stride 37: no 16-byte alignment
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+@pytest.mark.parametrize("tile", range(len(TILES)), ids=TILES)
+def test_ttt_16bit_vectors_along_n(T, tmp_path, dtype, tile):
+    """16-bit operand whose GEMM N dim has unit stride (A first-order, C
+    first-order): loaded as 16-byte vectors of eight columns and stored
+    transposed into the LDS slice, for every tile shape (forced through a
+    one-entry kernel table), with ragged N, column runs that end inside a
+    wave (such waves load column by column), a K stride that rules vectors
+    out, and K long enough for several slices and a split (Sec. 5.2 Eq. ttt)."""
+    import torch
+    g = synth.rng(72, tile + (0 if dtype == "bf16" else 7))
+    for fa, ka, fb, pad, vec in VEC_CASES:
+        na, nb = fa + ka, ka + fb
+        q, r, s_ = len(ka), len(fa), len(fb)
+        phi = tuple(range(1, len(na) + 1))
+        psi = tuple(range(q + 1, q + s_ + 1)) + tuple(range(1, q + 1))
+        X, Y = synth.uniform(na, g), synth.uniform(nb, g)
+        Xr, Yr = round_to(X, dtype), round_to(Y, dtype)
+        ref = np.asarray(oracle.ttt(oracle.materialize(Xr), oracle.materialize(Yr), q, phi, psi))
+        if pad:
+            Xp = np.zeros((pad,) + na[1:])
+            Xp[: na[0]] = X
+            Ad = to_gpu(Xp, None, dtype)[: na[0]]
+        else:
+            Ad = to_gpu(X, None, dtype)
+        Bd = to_gpu(Y, None, dtype)
+        C = T.empty(fa + fb, None, torch.float32, "cuda")
+        prev = T.set_autotune("frozen")
+        try:
+            _force_ttt_tile(T, tmp_path, Ad, Bd, C, q, phi, psi, tile)
+            plan = T.plan(T.ttt, Ad, Bd, q, phi, psi, out=C)
+            C.fill_(float("nan"))
+            T.ttt(Ad, Bd, q, phi, psi, out=C)
+        finally:
+            T.autotune_clear()
+            T.set_autotune(prev)
+        assert "tile=%s" % TILES[tile] in plan and "autotuned" in plan, plan
+        assert (_yvec(plan) == 8) == vec, plan
+        assert_close(to_np(C), ref, TOL_KERNEL16, "%s %s %s" % (plan, dtype, na))
