@@ -126,10 +126,9 @@ int tlib_ttt(const tlib_tensor* A, const tlib_tensor* B, int32_t q,
 /* tlib_ttt for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * same operation, arguments and errors as tlib_ttt, but no workspace.  Its
- * split-K partials (and the split's per-tile counters, 64 KiB) live in a
- * static device array of TLIB_NOALLOC_SCRATCH_BYTES per GPU, part of the
- * library's code object and held until the process ends; the split is
- * bounded by that size (a product
+ * split-K partials live in a static device array of
+ * TLIB_NOALLOC_SCRATCH_BYTES per GPU, part of the library's code object and
+ * held until the process ends; the split is bounded by that size (a product
  * whose single slice would not fit runs unsplit, so no size is refused; a
  * plan that needed more would return TLIB_ENOMEM before launching).  The tile
  * is the planner's rule (no autotuning).  The call allocates nothing and never

@@ -260,17 +260,10 @@ bool capturing(hipStream_t s) {
 static constexpr size_t WS_ALIGN = 256;
 static size_t ws_round(size_t b) { return (b + WS_ALIGN - 1) / WS_ALIGN * WS_ALIGN; }
 
-// A new buffer: its counter region (the last WS_COUNTER_BYTES) starts at zero.
-// The fill runs on the stream that allocates, never while it captures.
-static void* ws_alloc(size_t bytes, hipStream_t s) {
+static void* ws_alloc(size_t bytes) {
     void* p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
-        return nullptr;
-    }
-    if (hipMemsetAsync(static_cast<char*>(p) + bytes - WS_COUNTER_BYTES, 0, WS_COUNTER_BYTES, s) != hipSuccess) {
-        (void)hipGetLastError();
-        (void)hipFree(p);
         return nullptr;
     }
     return p;
@@ -287,9 +280,8 @@ void* WsCtx::take(size_t bytes) {
         WsBuf& e = g_ws[{dev, s}];
         if (!e.ptr) {
             if (capturing(s)) return nullptr;  // no allocation while a graph is captured
-            const size_t want = std::max({ws_round(hint) + WS_COUNTER_BYTES, used + bytes + WS_COUNTER_BYTES,
-                                          size_t(TLIB_WORKSPACE_DEFAULT_BYTES)});
-            void* p = ws_alloc(want, s);
+            const size_t want = std::max({ws_round(hint), used + bytes, size_t(TLIB_WORKSPACE_DEFAULT_BYTES)});
+            void* p = ws_alloc(want);
             if (!p) return nullptr;
             e.ptr = static_cast<char*>(p);
             e.bytes = want;
@@ -297,7 +289,7 @@ void* WsCtx::take(size_t bytes) {
         base = e.ptr;
         size = e.bytes;
     }
-    if (used + bytes > avail_total()) return nullptr;
+    if (used + bytes > size) return nullptr;
     void* p = base + used;
     used += bytes;
     return p;
@@ -374,11 +366,6 @@ static int exec_launch(const Launch& L, const void* in0, const void* in1, void* 
         P.Y = L.xsrc ? in0 : in1;
         P.C = out;
         P.part = w;
-        // split-K sums in the kernel (the last slice of a tile to finish)
-        // when the buffer's counters cover every tile
-        P.cnt = nullptr;
-        if (P.ksplit > 1 && ws.base && int64_t(P.tiles_m) * P.tiles_n <= int64_t(WS_COUNTER_BYTES / 4))
-            P.cnt = ws.counters();
         rc = launch_gemm(L.dtype, L.i0, P, s);
     } else if (L.kind == LK_GEMM_GENERIC) {
         rc = launch_gemm_generic(L.dtype, L.xsrc ? in1 : in0, L.xsrc ? in0 : in1, out, L.gd[0], L.gd[1], L.gd[2], s);
@@ -1807,7 +1794,7 @@ int tlib_ttt_noalloc(const tlib_tensor* A, const tlib_tensor* B, int32_t q, cons
     }
     Launch N;
     if (q != 0 || plan_outer(a, b, phi, psi, c, N) != TLIB_OK) {
-        rc = plan_ttt(a, b, q, phi, psi, c, TLIB_NOALLOC_SCRATCH_BYTES - WS_COUNTER_BYTES, N, -1);
+        rc = plan_ttt(a, b, q, phi, psi, c, TLIB_NOALLOC_SCRATCH_BYTES, N, -1);
         if (rc) return rc;
     }
     rc = exec_launch(N, a.data, b.data, c.data, ws, st);
@@ -2267,9 +2254,8 @@ int tlib_workspace_reserve(void* stream, size_t bytes) {
     std::lock_guard<std::mutex> lk(g_ws_mu);
     WsBuf& e = g_ws[{dev, s}];
     if (e.ptr && e.bytes >= bytes) return TLIB_OK;
-    bytes += WS_COUNTER_BYTES;
-    void* p = ws_alloc(bytes, s);
-    if (!p) return fail(TLIB_ENOMEM, "workspace_reserve: allocation of %zu bytes failed", bytes);
+    void* p = ws_alloc(bytes);
+    if (!p) return fail(TLIB_ENOMEM, "workspace_reserve: hipMalloc of %zu bytes failed", bytes);
     if (e.ptr) e.retired.push_back(e.ptr);  // graphs captured earlier may still use it
     e.ptr = static_cast<char*>(p);
     e.bytes = bytes;

@@ -115,8 +115,6 @@ struct GemmParams {
     int32_t y_vec;           // > 0: Y loaded as vectors of y_vec elements along N (K one dim, stride syk)
     int64_t syk;
     int32_t kvec;            // bit 0 / bit 1: X / Y loaded as groups of consecutive k (8 for 16-bit, 2 for FP32/FP64)
-    int32_t* cnt;            // split-K: per-tile arrival counters (zero on entry, left zero); null = sum in a
-                             // second kernel
 };
 
 // Multi-mode TTV (one pass over A).  A group of modes in storage order,
@@ -318,10 +316,6 @@ int launch_axpby_tile(int in_dtype, int out_dtype, double alpha, const void* A, 
 // or a fixed buffer the caller brings (`fixed`).  take() hands out 256-byte
 // aligned pieces from the start and returns nullptr when the buffer cannot
 // hold them (or cannot be allocated); it never frees or waits.
-// The last WS_COUNTER_BYTES of every buffer hold per-tile counters of the
-// split-K GEMM (zero when the buffer is created; each kernel that uses one
-// sets it back to zero), so they are not handed out by take().
-constexpr size_t WS_COUNTER_BYTES = size_t(64) << 10;
 struct WsCtx {
     hipStream_t s = nullptr;
     char* base = nullptr;
@@ -331,9 +325,7 @@ struct WsCtx {
     bool fixed = false;
     void* take(size_t bytes);
     void need(size_t bytes);
-    size_t avail_total() const { return size > WS_COUNTER_BYTES ? size - WS_COUNTER_BYTES : 0; }
-    size_t avail() const { return avail_total() > used ? avail_total() - used : 0; }
-    int32_t* counters() const { return reinterpret_cast<int32_t*>(base + size - WS_COUNTER_BYTES); }
+    size_t avail() const { return size > used ? size - used : 0; }
 };
 
 }  // namespace tlib

@@ -425,8 +425,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
     constexpr int RQ = std::is_same<TI, double>::value ? 1 : 4;
     constexpr int RR = std::is_same<TI, double>::value ? 4 : 1;
     if (P.ksplit > 1) {
-        const int64_t MN = int64_t(P.M) * P.N;
-        TA* part = (TA*)P.part + int64_t(kz) * MN;
+        TA* part = (TA*)P.part + int64_t(kz) * P.M * P.N;
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
             const int col = n0 + wn0 + j * 16 + rl;
@@ -439,31 +438,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
                     if (row < P.M) part[int64_t(row) * P.N + col] = acc[i][j][r];
                 }
         }
-        if (!P.cnt) return;  // gemm_ksum_kernel sums the partials
-        // The slice of this tile that finishes last sums all slices' partials
-        // in slice order (the order of gemm_ksum_kernel) and writes C, then
-        // sets the tile's counter back to zero for the next call.  The fences
-        // make the partials visible across the device (other XCDs' L2s)
-        // before the count, and the count before they are read.
-        __shared__ int s_last;
-        __threadfence();
-        __syncthreads();
-        if (tid == 0) s_last = atomicAdd(&P.cnt[bid], 1) == P.ksplit - 1;
-        __syncthreads();
-        if (!s_last) return;
-        __threadfence();
-        const TA* pp = (const TA*)P.part;
-        TA* C = (TA*)P.C;
-        for (int e = tid; e < BM * BN; e += 256) {
-            const int r = e / BN, c = e - (e / BN) * BN;
-            const int row = m0 + r, col = n0 + c;
-            if (row >= P.M || col >= P.N) continue;
-            const int64_t o = int64_t(row) * P.N + col;
-            TA sum = __builtin_nontemporal_load(pp + o);
-            for (int z = 1; z < P.ksplit; ++z) sum += __builtin_nontemporal_load(pp + int64_t(z) * MN + o);
-            C[crow[r] + ccol[c]] = sum;
-        }
-        if (tid == 0) P.cnt[bid] = 0;
         return;
     }
     // Staged epilogue: each wave writes one 16-row block of its tile to LDS,
@@ -584,7 +558,7 @@ static int gemm_launch(const GemmParams& p, hipStream_t s) {
     }
 #undef TLIB_GEMM
     if (hipGetLastError() != hipSuccess) return TLIB_EHIP;
-    if (p.ksplit > 1 && !p.cnt) {
+    if (p.ksplit > 1) {
         const int64_t MN = int64_t(p.M) * p.N;
         const unsigned g = unsigned(std::min<int64_t>((MN + 255) / 256, 65536));
         hipLaunchKernelGGL((gemm_ksum_kernel<TA>), dim3(g), dim3(256), 0, s, p);
