@@ -318,7 +318,7 @@ static int ws_fail(const WsCtx& ws, size_t bytes, const char* op) {
 
 enum LaunchKind {
     LK_NONE = 0, LK_TTV_COLW, LK_TTV_COL, LK_TTV_SLAB, LK_TTV_FIBER, LK_TTV_GENERIC,
-    LK_GEMM, LK_GEMM_GENERIC, LK_TTM_STREAM, LK_TTM_ROWS, LK_OUTER
+    LK_GEMM, LK_GEMM_GENERIC, LK_TTM_STREAM, LK_TTM_ROWS, LK_OUTER, LK_GEMM_ROWS
 };
 
 struct Launch {
@@ -367,6 +367,14 @@ static int exec_launch(const Launch& L, const void* in0, const void* in1, void* 
         P.C = out;
         P.part = w;
         rc = launch_gemm(L.dtype, L.i0, P, s);
+    } else if (L.kind == LK_GEMM_ROWS) {
+        GemmParams P = L.gemm;
+        P.X = L.xsrc ? in1 : in0;
+        P.Y = L.xsrc ? in0 : in1;
+        P.C = out;
+        P.part = w;
+        rc = launch_gemm_rows(L.dtype, L.i0, L.i1, P, s);
+        if (rc == TLIB_OK && P.ksplit > 1) rc = launch_gemm_ksum(acc_dtype(L.dtype), P, s);
     } else if (L.kind == LK_GEMM_GENERIC) {
         rc = launch_gemm_generic(L.dtype, L.xsrc ? in1 : in0, L.xsrc ? in0 : in1, out, L.gd[0], L.gd[1], L.gd[2], s);
     } else if (L.kind == LK_TTM_STREAM) {
@@ -923,6 +931,65 @@ static int plan_gemm(int dtype, int x_is, const void* X, const void* Y, void* C,
             if (groups_ok(0, X, dm, ndm)) P.kvec |= 1;
             if (P.y_vec == 0 && groups_ok(1, Y, dn, ndn)) P.kvec |= 2;
         }
+        // The all-rows kernel (M <= 128 in one tile, Y streamed straight into
+        // the MFMAs): X's K groups must be contiguous (16 bytes; FP32 8), and
+        // for 16-bit inputs Y's as well.  Chosen only by the autotuner (picks
+        // from 3 GT_COUNT on: 64 fn columns per workgroup, fn = 1 + r % 2,
+        // split target 1024 >> (r / 2)).
+        {
+            const bool wide = dtype == TLIB_BF16 || dtype == TLIB_F16;
+            const int gx = wide ? 8 : 2;
+            auto k_groups = [&](int o, const void* base, const Dim* d, int nd, int gv) {
+                if (ndk < 1 || dk[0].n % gv != 0 || dk[0].s[o] != 1 ||
+                    (uintptr_t(base) % (size_t(gv) * esize(dtype))) != 0)
+                    return false;
+                for (int i = 1; i < ndk; ++i)
+                    if (dk[i].s[o] % gv != 0) return false;
+                for (int i = 0; i < nd; ++i)
+                    if (d[i].s[0] % gv != 0) return false;
+                return true;
+            };
+            const bool rows_ok = M <= 128 && k_groups(0, X, dm, ndm, gx) && (!wide || k_groups(1, Y, dn, ndn, 8));
+            const bool forced = tile_force >= 3 * GT_COUNT && tile_force < 3 * GT_COUNT + 6;
+            if (forced && !rows_ok) return PICK_NA;
+            if (rows_ok && forced) {
+                const int r = forced ? tile_force - 3 * GT_COUNT : 0;
+                const int fn = 1 + r % 2, target = 1024 >> (r / 2);
+                int fm = 1;
+                while (16 * fm < M) fm *= 2;
+                const int64_t tiles = (N + 64 * fn - 1) / (64 * fn);
+                const int kc = gemm_rows_kchunk(dtype);
+                int ks = 1;
+                if (tiles < target) {
+                    const int64_t want = (target + tiles - 1) / tiles;
+                    const int64_t maxk = std::max<int64_t>(1, K / (4 * kc));
+                    ks = int(std::min<int64_t>(std::min<int64_t>(want, maxk), 32));
+                }
+                P.kchunk = int32_t(((K + ks - 1) / ks + kc - 1) / kc * kc);
+                P.ksplit = int((K + P.kchunk - 1) / P.kchunk);
+                if (ws_cap != SIZE_MAX && P.ksplit > 1) {
+                    const size_t per = size_t(M) * size_t(N) * size_t(esize(acc_dtype(dtype)));
+                    const int cap = int(std::max<int64_t>(1, std::min<int64_t>(P.ksplit, int64_t(ws_cap / per))));
+                    if (cap < P.ksplit) {
+                        P.kchunk = int32_t(((K + cap - 1) / cap + kc - 1) / kc * kc);
+                        P.ksplit = int((K + P.kchunk - 1) / P.kchunk);
+                    }
+                }
+                P.tiles_m = 1;
+                P.tiles_n = int32_t(tiles);
+                plan_note("%s gemm-rows dtype=%s M=%lld N=%lld K=%lld dims=(%d,%d,%d) fm=%d fn=%d ksplit=%d tiles=%lld",
+                          op, dname(dtype), (long long)M, (long long)N, (long long)K, ndm, ndn, ndk, fm, fn,
+                          P.ksplit, (long long)tiles);
+                L.kind = LK_GEMM_ROWS;
+                P.X = P.Y = nullptr;
+                P.C = nullptr;
+                L.gemm = P;
+                L.i0 = fm;
+                L.i1 = fn;
+                L.wsb = P.ksplit > 1 ? size_t(P.ksplit) * size_t(M) * size_t(N) * size_t(esize(acc_dtype(dtype))) : 0;
+                return TLIB_OK;
+            }
+        }
         // FP64 accumulators are twice as wide: keep a wave's tile at 64x32 so
         // that two waves fit per SIMD.
         const bool wide_acc = dtype == TLIB_F64;
@@ -1345,9 +1412,13 @@ static int plan_ttm(const Ten& a, const Ten& bm, int mi, const Ten& c, int pick,
     for (int r = 0; r < a.p; ++r)
         if (r != mi) dn[ndn++] = {a.n[r], {a.w[r], c.w[r], 0}};
     Dim dk[1] = {{a.n[mi], {bm.w[1], a.w[mi], 0}}};
-    const int tile = pick >= TTM_PICK_GEMM ? pick - TTM_PICK_GEMM : -1;
-    return plan_gemm(a.dtype, 1, bm.data, a.data, c.data, dm, 1, dn, ndn, dk, 1, "ttm", SIZE_MAX, L,
-                     tile < GT_COUNT ? tile : -1);
+    // TTM_PICK_GEMM + t: t < GT_COUNT a tile, GT_COUNT the GEMM's own rule,
+    // GT_COUNT + 1 + r the all-rows kernel variant r (0..5)
+    const int t = pick >= TTM_PICK_GEMM ? pick - TTM_PICK_GEMM : -1;
+    int force = -1;
+    if (t >= 0 && t < GT_COUNT) force = t;
+    else if (t > GT_COUNT && t <= GT_COUNT + 6) force = 3 * GT_COUNT + (t - GT_COUNT - 1);
+    return plan_gemm(a.dtype, 1, bm.data, a.data, c.data, dm, 1, dn, ndn, dk, 1, "ttm", SIZE_MAX, L, force);
 }
 
 // Plan and launch one TTM (no plan cache): the pieces of a ttm2 chain.
@@ -1440,7 +1511,7 @@ int tlib_ttm(const tlib_tensor* A, const tlib_tensor* B, int32_t m, const tlib_t
     }
     static const int cands[] = {TTM_PICK_STREAM,          TTM_PICK_ROWS_PLAIN,        TTM_PICK_GEMM + GT_COUNT,
                                 TTM_PICK_GEMM + GT_128x64, TTM_PICK_GEMM + GT_128x128, TTM_PICK_GEMM + GT_64x128,
-                                TTM_PICK_GEMM + GT_256x64};
+                                TTM_PICK_GEMM + GT_256x64, TTM_PICK_GEMM + GT_COUNT + 1, TTM_PICK_GEMM + GT_COUNT + 2};
     std::string key = "ttm";
     key_int(key, m);
     key_ten(key, a);
@@ -1750,8 +1821,11 @@ int tlib_ttt(const tlib_tensor* A, const tlib_tensor* B, int32_t q, const int32_
         if (r == TLIB_OK) last = std::move(N);
         return r;
     };
-    // every tile with three split targets (about 1024, 512 and 256 workgroups)
-    static const int cands[] = {GT_16x256, GT_64x128, GT_128x128, GT_256x64, GT_64x64, GT_128x64, GT_256x32,
+    // every tile with three split targets (about 1024, 512 and 256
+    // workgroups), then the all-rows kernel (64 or 128 columns per workgroup)
+    // with the same three targets
+    static const int cands[] = {3 * GT_COUNT + 0, 3 * GT_COUNT + 1, 3 * GT_COUNT + 2, 3 * GT_COUNT + 3,
+                                3 * GT_COUNT + 4, 3 * GT_COUNT + 5, GT_16x256, GT_64x128, GT_128x128, GT_256x64, GT_64x64, GT_128x64, GT_256x32,
                                 GT_COUNT + GT_16x256, GT_COUNT + GT_64x128, GT_COUNT + GT_128x128,
                                 GT_COUNT + GT_256x64, GT_COUNT + GT_64x64, GT_COUNT + GT_128x64,
                                 GT_COUNT + GT_256x32, 2 * GT_COUNT + GT_16x256, 2 * GT_COUNT + GT_64x128,

@@ -276,6 +276,13 @@ int launch_ttv_fiber(int dtype, const TtvParams& p, const Grp& go, int G, hipStr
 
 int launch_gemm(int dtype, int tile, const GemmParams& p, hipStream_t s);
 int gemm_slice_k(int dtype, int tile);  // K depth of one LDS slice of the tile
+// All-rows GEMM (k_gemm_rows.hip) for M <= 16 fm: fm in {1, 2, 4, 8}, 64 fn
+// columns per workgroup, fn in {1, 2}.  Needs X's K groups contiguous (16
+// bytes, FP32 8) and, for 16-bit inputs, Y's as well (kvec bits 0 and 1).
+int launch_gemm_rows(int dtype, int fm, int fn, const GemmParams& p, hipStream_t s);
+int gemm_rows_kchunk(int dtype);  // K per chunk (the split granularity)
+// Sum of split-K partials [ksplit][M][N] into C (acc_dtype = FP32 or FP64).
+int launch_gemm_ksum(int acc_dtype, const GemmParams& p, hipStream_t s);
 // prep + main + finish kernels of the one-pass multi-mode TTV; vec: 16-byte loads
 int launch_tv(int dtype, const TvParams& P, void* c, int64_t cs, bool vec, hipStream_t s);
 int launch_ttm2(int dtype, const Ttm2Params& P, bool vec, hipStream_t s);

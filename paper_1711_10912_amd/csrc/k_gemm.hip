@@ -581,6 +581,14 @@ static int gemm_dispatch(int tile, const GemmParams& p, hipStream_t s) {
     return TLIB_EINVAL;
 }
 
+int launch_gemm_ksum(int acc_dtype, const GemmParams& p, hipStream_t s) {
+    const int64_t MN = int64_t(p.M) * p.N;
+    const unsigned g = unsigned(std::min<int64_t>((MN + 255) / 256, 65536));
+    if (acc_dtype == TLIB_F64) hipLaunchKernelGGL((gemm_ksum_kernel<double>), dim3(g), dim3(256), 0, s, p);
+    else hipLaunchKernelGGL((gemm_ksum_kernel<float>), dim3(g), dim3(256), 0, s, p);
+    return hipGetLastError() == hipSuccess ? TLIB_OK : TLIB_EHIP;
+}
+
 template <typename TI>
 static int slice_k(int tile) {
     switch (tile) {
