@@ -274,6 +274,35 @@ def test_add_scale_transpose(T, dtype):
             assert np.array_equal(to_np(Tt), np.transpose(Xr, [t - 1 for t in tau]))
 
 
+@pytest.mark.parametrize("din,dout", [("f64", "f64"), ("f32", "f32"), ("bf16", "bf16"), ("f16", "f16"),
+                                      ("f32", "bf16"), ("f64", "f32"), ("bf16", "f32")])
+def test_add_scale_flat_vectors(T, din, dout):
+    """Sec. 5.1 Eq. transform / scaling on one unit-stride run long enough for
+    the 16-byte vector path, with a ragged tail: every element equal to the
+    correctly rounded FP64 value, in place as well."""
+    import torch
+    from _util import torch_dtype
+    g = synth.rng(19, 40 + DTYPES.index(din) * 4 + DTYPES.index(dout))
+    n = (1 << 20) + 5
+    X, Y = synth.uniform((n,), g), synth.uniform((n,), g)
+    Xr, Yr = round_to(X, din), round_to(Y, din)
+    Ad, Bd = to_gpu(X, None, din), to_gpu(Y, None, din)
+    if din == dout:
+        assert "flat" in T.plan(T.add, 0.75, Ad, -1.25, Bd, out=T.empty((n,), None, torch_dtype(din), "cuda"))
+        C = T.add(0.75, Ad, -1.25, Bd)
+        ref = oracle.axpby(0.75, oracle.materialize(Xr), -1.25, oracle.materialize(Yr))
+        assert np.array_equal(to_np(C), correctly_rounded(np.asarray(ref), dout))
+        T.add(0.75, Ad, -1.25, Bd, out=Ad)
+        assert np.array_equal(to_np(Ad), correctly_rounded(np.asarray(ref), dout))
+        Ad = to_gpu(X, None, din)
+    S = T.scale(-3.0, Ad, dtype=torch_dtype(dout))
+    ref = oracle.scale(-3.0, oracle.materialize(Xr))
+    assert np.array_equal(to_np(S), correctly_rounded(np.asarray(ref), dout))
+    # an odd offset into the buffer: not 16-byte aligned, the element path
+    S2 = T.scale(-3.0, Ad[1:], dtype=torch_dtype(dout))
+    assert np.array_equal(to_np(S2), correctly_rounded(np.asarray(ref)[1:], dout))
+
+
 def test_add_in_place(T):
     g = synth.rng(20, 0)
     X, Y = synth.integers((40, 30), g), synth.integers((40, 30), g)
