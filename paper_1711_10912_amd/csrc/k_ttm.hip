@@ -23,6 +23,11 @@ namespace tlib {
 
 typedef double d4s_t __attribute__((ext_vector_type(4)));
 typedef float f4s_t __attribute__((ext_vector_type(4)));
+
+// Element p of the result holds element p ^ g of a (g in 0..3).
+__device__ __forceinline__ f4s_t swz4(f4s_t a, int g) {
+    return g == 0 ? a : g == 1 ? a.yxwz : g == 2 ? a.zwxy : a.wzyx;
+}
 typedef __bf16 bf8s_t __attribute__((ext_vector_type(8)));
 typedef _Float16 h8s_t __attribute__((ext_vector_type(8)));
 typedef uint32_t u4s_t __attribute__((ext_vector_type(4)));
@@ -290,7 +295,17 @@ __global__ __launch_bounds__(256) void ttm_rows_kernel(TtmRowParams P) {
     RT* Bs = reinterpret_cast<RT*>(smem);
     const int bbytes = ((WIDE ? M16 * PB : KP * PB) * int(sizeof(RT)) + 15) & ~15;
     TA* stg = reinterpret_cast<TA*>(smem + bbytes) + wave * STG;
-    auto stage_at = [&](int row, int col) -> TA { return F64 ? stg[row * SP + col] : stg[col * SPC + row]; };
+    // FP32 staging in the plain and band-wide modes puts row r of column c at
+    // position r ^ ((c >> 4) & 3) of the column: the four columns c, c+16,
+    // c+32, c+48 whose pitch-20 starts share a bank quad then hold a given
+    // row on four different banks, so a read of one row across 64
+    // consecutive columns is free of conflicts.  (In the aligned and narrow
+    // band modes the extra address arithmetic measured slower than the
+    // conflicts it removes.)
+    constexpr bool SWZ = !F64 && (MODE == TTM_ROWS_PLAIN || MODE == TTM_ROWS_BANDW);
+    auto stage_at = [&](int row, int col) -> TA {
+        return F64 ? stg[row * SP + col] : stg[col * SPC + (SWZ ? row ^ ((col >> 4) & 3) : row)];
+    };
     const TI* X = (const TI*)P.X;
     const TI* Y = (const TI*)P.Y;
     TA* C = (TA*)P.C;
@@ -367,7 +382,9 @@ __global__ __launch_bounds__(256) void ttm_rows_kernel(TtmRowParams P) {
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(base, 0, int(nbytes), 0x00020000);
         // Stage layout: FP64 row-major, the four rows kq of result register
         // pc; FP32 column-major with the four rows 4kq..4kq+3 of a result
-        // register written as one 16-byte vector, all sixteen rows at piece 0.
+        // register written as one 16-byte vector (permuted as stage_at reads
+        // it: column j*16+rl has (c >> 4) & 3 == j & 3), all sixteen rows at
+        // piece 0.
         // (Row-major FP32 staging with scalar stores was miscompiled by hipcc
         // for gfx950: two stores merged into a ds_write2_b32 with a wrong
         // first offset.)
@@ -375,7 +392,7 @@ __global__ __launch_bounds__(256) void ttm_rows_kernel(TtmRowParams P) {
 #pragma unroll
             for (int j = 0; j < FN; ++j) {
                 if constexpr (F64) stg[kq * SP + j * 16 + rl] = acc[j][pc];
-                else *reinterpret_cast<f4s_t*>(&stg[(j * 16 + rl) * SPC + 4 * kq]) = acc[j];
+                else *reinterpret_cast<f4s_t*>(&stg[(j * 16 + rl) * SPC + 4 * kq]) = swz4(acc[j], SWZ ? j & 3 : 0);
             }
         }
         const int r0 = F64 ? 0 : 4 * pc;  // first staged row of this piece
