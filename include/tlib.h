@@ -329,7 +329,13 @@ const char* tlib_last_plan(void);
  *                         one call synchronous, and keeps the fastest; later
  *                         calls of the shape use the stored choice;
  *   TLIB_AUTOTUNE_FROZEN  stored choices are used, new shapes get the rules.
- * Calls on a stream that is capturing a graph never tune.  The table is
+ * Each tuned choice is stored twice: for the exact call shape and for its
+ * shape class (op, dtype, which operands hold their smallest stride in a
+ * contracted mode, where C holds its smallest stride, and the base-4
+ * logarithms of the problem's extents), the first tuned shape of a class
+ * giving the class its choice.  A call shape
+ * with no exact entry takes its class's choice in FROZEN mode and is tuned
+ * in ON mode.  Calls on a stream that is capturing a graph never tune.  The table is
  * shared by all threads and guarded by a lock.  tlib_autotune_entries
  * returns the number of stored choices; tlib_autotune_clear empties the
  * table.  Candidates differ only in summation order inside the MFMAs, so

@@ -327,6 +327,7 @@ struct Launch {
     int i0 = 0, i1 = 0, i2 = 0;  // kernel-specific: vec/ks/kr, slabs/kc, G, tile, fm/mode, ks, grid
     int xsrc = 0;                // GEMM: X is operand 0 (A) or 1 (B / b) of the call
     size_t wsb = 0;              // scratch bytes taken from the call's workspace
+    size_t xwsb = 0;             // GEMM: bytes of X packed into the workspace (gd[0]: the copy), or 0
     const char* op = "";
     TtvParams ttv{};
     Grp go{};
@@ -340,12 +341,22 @@ struct Launch {
 
 // in0 = A, in1 = b / B, out = C
 static int exec_launch(const Launch& L, const void* in0, const void* in1, void* out, WsCtx& ws, hipStream_t s) {
-    ws.need(L.wsb);
+    ws.need(L.xwsb ? ws_round(L.wsb) + L.xwsb : L.wsb);
     if (g_plan_only) return TLIB_OK;
     void* w = nullptr;
     if (L.wsb) {
         w = ws.take(L.wsb);
         if (!w) return ws_fail(ws, L.wsb, L.op);
+    }
+    // GEMM with a packed X: copy X (gd[0]: its strides, the packed ones) into
+    // the workspace first
+    const void* xpk = nullptr;
+    if (L.xwsb) {
+        void* xp = ws.take(L.xwsb);
+        if (!xp) return ws_fail(ws, ws_round(L.wsb) + L.xwsb, L.op);
+        const int prc = launch_axpby(L.dtype, L.dtype, 1.0, L.xsrc ? in1 : in0, 0.0, nullptr, xp, L.gd[0], s);
+        if (prc) return fail(prc, "%s: packing X failed", L.op);
+        xpk = xp;
     }
     int rc = TLIB_EHIP;
     if (L.kind >= LK_TTV_COLW && L.kind <= LK_TTV_GENERIC) {
@@ -362,14 +373,14 @@ static int exec_launch(const Launch& L, const void* in0, const void* in1, void* 
         }
     } else if (L.kind == LK_GEMM) {
         GemmParams P = L.gemm;
-        P.X = L.xsrc ? in1 : in0;
+        P.X = xpk ? xpk : L.xsrc ? in1 : in0;
         P.Y = L.xsrc ? in0 : in1;
         P.C = out;
         P.part = w;
         rc = launch_gemm(L.dtype, L.i0, P, s);
     } else if (L.kind == LK_GEMM_ROWS) {
         GemmParams P = L.gemm;
-        P.X = L.xsrc ? in1 : in0;
+        P.X = xpk ? xpk : L.xsrc ? in1 : in0;
         P.Y = L.xsrc ? in0 : in1;
         P.C = out;
         P.part = w;
@@ -752,8 +763,9 @@ static std::string ttt_class_key(const Ten& a, const Ten& b, const Ten& c, int q
 // tuned), so a plan cache may keep it; false when tuning was due but could
 // not run (plan-only mode, a capturing stream).
 // A shape without its own entry takes the entry of its class (ckey) when the
-// table has one; tuning a new shape stores its pick under both keys (the class
-// entry only if the class has none yet).
+// table has one and the mode is frozen; in ON mode it is tuned.  Tuning a new
+// shape stores its pick under both keys (the class entry only if the class has
+// none yet).
 template <class F>
 static int tuned(const std::string& key, const std::string& ckey, const int* cands, int nc, hipStream_t s, F&& run,
                  bool* settled) {
@@ -772,7 +784,8 @@ static int tuned(const std::string& key, const std::string& ckey, const int* can
             by_class = true;
         }
     }
-    if (pick != PICK_NA) {
+    // in ON mode a shape with only a class entry is tuned for itself
+    if (pick != PICK_NA && !(by_class && mode == TLIB_AUTOTUNE_ON)) {
         const int rc = run(pick);
         if (rc != PICK_NA) {
             g_plan += by_class ? " autotuned(class)" : " autotuned";
@@ -877,6 +890,43 @@ static int plan_gemm(int dtype, int x_is, const void* X, const void* Y, void* C,
     // loads run along memory.
     ndk = coalesce(dk, ndk, 2, M > N ? 0 : 1);
 
+    // Packed X: a small X (at most 4M elements and a sixteenth of Y's bytes)
+    // whose first K dim does not have unit stride while Y's does is copied
+    // into the workspace as an M x K matrix with k fastest, in the K order
+    // chosen above, so that the GEMM loads groups of consecutive k from both
+    // operands (16-bit MFMA operands take eight, FP32/FP64 loads two).  The
+    // copy's dims are K's then M's, with X's strides and the packed ones.
+    GDims xpack{};
+    size_t xwsb = 0;
+    Dim dm0[MAXP], dk0[MAXP];
+    const void* X0 = X;
+    for (int i = 0; i < ndm; ++i) dm0[i] = dm[i];
+    for (int i = 0; i < ndk; ++i) dk0[i] = dk[i];
+    {
+        const int gv = (dtype == TLIB_BF16 || dtype == TLIB_F16) ? 8 : 2;
+        if (ws_cap == SIZE_MAX && ndk >= 1 && ndk + ndm <= MAXP && dk[0].s[0] != 1 && dk[0].s[1] == 1 &&
+            dk[0].n % gv == 0 && M * K <= (int64_t(1) << 22) && 16 * M <= N && K >= 64) {
+            int64_t st = 1;
+            for (int i = 0; i < ndk; ++i) {
+                xpack.n[xpack.nd] = dk[i].n;
+                xpack.s[0][xpack.nd] = dk[i].s[0];
+                xpack.s[2][xpack.nd++] = st;
+                dk[i].s[0] = st;
+                st *= dk[i].n;
+            }
+            for (int i = 0; i < ndm; ++i) {
+                xpack.n[xpack.nd] = dm[i].n;
+                xpack.s[0][xpack.nd] = dm[i].s[0];
+                xpack.s[2][xpack.nd++] = st;
+                dm[i].s[0] = st;
+                st *= dm[i].n;
+            }
+            xpack.total = st;
+            xwsb = size_t(st) * size_t(esize(dtype));
+            X = reinterpret_cast<const void*>(uintptr_t(WS_ALIGN));  // workspace pieces are 256-byte aligned
+        }
+    }
+
     GemmParams P{};
     bool fast = fill_grp(P.gm, dm, ndm, 0, 1) && fill_grp(P.gn, dn, ndn, 0, 1) &&
                 fill_grp(P.gk, dk, ndk, 0, 1);
@@ -980,12 +1030,15 @@ static int plan_gemm(int dtype, int x_is, const void* X, const void* Y, void* C,
                 plan_note("%s gemm-rows dtype=%s M=%lld N=%lld K=%lld dims=(%d,%d,%d) fm=%d fn=%d ksplit=%d tiles=%lld",
                           op, dname(dtype), (long long)M, (long long)N, (long long)K, ndm, ndn, ndk, fm, fn,
                           P.ksplit, (long long)tiles);
+                if (xwsb) g_plan += " xpack";
                 L.kind = LK_GEMM_ROWS;
                 P.X = P.Y = nullptr;
                 P.C = nullptr;
                 L.gemm = P;
                 L.i0 = fm;
                 L.i1 = fn;
+                L.gd[0] = xpack;
+                L.xwsb = xwsb;
                 L.wsb = P.ksplit > 1 ? size_t(P.ksplit) * size_t(M) * size_t(N) * size_t(esize(acc_dtype(dtype))) : 0;
                 return TLIB_OK;
             }
@@ -1038,13 +1091,23 @@ static int plan_gemm(int dtype, int x_is, const void* X, const void* Y, void* C,
                   "cvec=%d yvec=%d kvec=%d ksplit=%d tiles=%lld",
                   op, dname(dtype), (long long)M, (long long)N, (long long)K, ndm, ndn, ndk, ts.bm,
                   ts.bn, P.x_kfast, P.y_kfast, P.c_vec, P.y_vec, P.kvec, P.ksplit, (long long)nt);
+        if (xwsb) g_plan += " xpack";
         L.kind = LK_GEMM;
         P.X = P.Y = nullptr;
         P.C = nullptr;
         L.gemm = P;
         L.i0 = tile;
         L.wsb = P.ksplit > 1 ? wsb : 0;
+        L.gd[0] = xpack;
+        L.xwsb = xwsb;
         return TLIB_OK;
+    }
+    if (xwsb) {
+        // the generic kernel reads X where it lies
+        for (int i = 0; i < ndm; ++i) dm[i] = dm0[i];
+        for (int i = 0; i < ndk; ++i) dk[i] = dk0[i];
+        X = X0;
+        xwsb = 0;
     }
     GDims gm, gn, gk;
     fill_gdims(gm, dm, ndm, 2);

@@ -47,12 +47,12 @@ template <> struct RowsCfg<float> {
     using xg_t = ru2_t;
 };
 template <> struct RowsCfg<bf16_t> {
-    static constexpr int KSTEP = 32, KC = 64, G = 8;
+    static constexpr int KSTEP = 32, KC = 128, G = 8;
     using acc_t = rf4_t;
     using xg_t = ru4_t;
 };
 template <> struct RowsCfg<f16_t> {
-    static constexpr int KSTEP = 32, KC = 64, G = 8;
+    static constexpr int KSTEP = 32, KC = 128, G = 8;
     using acc_t = rf4_t;
     using xg_t = ru4_t;
 };
@@ -85,15 +85,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
     constexpr int NKS = KC / KSTEP;                   // k-steps per chunk
     constexpr int MR = 16 * FM;                       // rows (padded)
     constexpr int BN = 64 * FN;                       // columns per workgroup
-    // row pitch: KC elements plus 16 bytes, i.e. 144 bytes = 36 dwords, so the
-    // 16 rows of a fragment start in 16 different groups of four banks
+    // row pitch: KC elements plus 16 bytes (144 bytes = 36 dwords for FP32 and
+    // FP64 chunks, 272 = 68 for 16-bit ones), so the 16 rows of a fragment
+    // start in 16 different groups of four banks
     constexpr int PX = KC + 16 / int(sizeof(TI));
     static_assert((PX * int(sizeof(TI))) % 16 == 0, "16-byte rows");
     constexpr int NG = MR * KC / G;                   // X groups per chunk
     constexpr int EG = (NG + 255) / 256;              // groups per thread
     using RT = typename std::conditional<WIDE, uint16_t, TI>::type;
 
-    __shared__ __align__(16) RT Xs[2][MR * PX];
+    // X's two chunk buffers (dynamic: 70 KB for 128 rows of 16-bit chunks)
+    extern __shared__ __align__(16) unsigned char rows_smem[];
+    RT(*Xs)[MR * PX] = reinterpret_cast<RT(*)[MR * PX]>(rows_smem);
     __shared__ int64_t kx[2][KC], ky[2][KC];
     __shared__ int64_t xrow[MR], crow[MR];
 
@@ -252,8 +255,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
 
 template <typename TI, int FM, int FN>
 static int rows_launch(const GemmParams& p, hipStream_t s) {
+    using RT = typename std::conditional<sizeof(TI) == 2, uint16_t, TI>::type;
+    constexpr int KC = RowsCfg<TI>::KC;
+    const size_t lds = size_t(2) * 16 * FM * (KC + 16 / sizeof(TI)) * sizeof(RT);
+    if (lds > 65536 &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_rows_kernel<TI, FM, FN>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) != hipSuccess)
+        return TLIB_EHIP;
     const dim3 grid(unsigned((p.N + 64 * FN - 1) / (64 * FN)), unsigned(p.ksplit));
-    hipLaunchKernelGGL((gemm_rows_kernel<TI, FM, FN>), grid, dim3(256), 0, s, p);
+    hipLaunchKernelGGL((gemm_rows_kernel<TI, FM, FN>), grid, dim3(256), lds, s, p);
     if (hipGetLastError() != hipSuccess) return TLIB_EHIP;
     return TLIB_OK;
 }

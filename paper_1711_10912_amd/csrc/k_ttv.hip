@@ -65,29 +65,38 @@ __global__ __launch_bounds__(256) void ttv_col_kernel(TtvParams P, int64_t lo_ti
         const TI* Ap = (const TI*)P.A + hA + lo0 * P.sA_lo;
         const TI* b = (const TI*)P.b;
         int64_t k = kb + wave;
-        // four rows in flight per wave
-        for (; k + 12 < ke; k += 16) {
-            TA x0[VEC], x1[VEC], x2[VEC], x3[VEC];
-            if constexpr (VEC > 1) {
-                load_vec<TI, VEC>(Ap + k * P.sA_k, x0);
-                load_vec<TI, VEC>(Ap + (k + 4) * P.sA_k, x1);
-                load_vec<TI, VEC>(Ap + (k + 8) * P.sA_k, x2);
-                load_vec<TI, VEC>(Ap + (k + 12) * P.sA_k, x3);
-            } else {
-                x0[0] = to_acc(Ap[k * P.sA_k]);
-                x1[0] = to_acc(Ap[(k + 4) * P.sA_k]);
-                x2[0] = to_acc(Ap[(k + 8) * P.sA_k]);
-                x3[0] = to_acc(Ap[(k + 12) * P.sA_k]);
-            }
-            const TA b0 = to_acc(b[k * P.sb]), b1 = to_acc(b[(k + 4) * P.sb]);
-            const TA b2 = to_acc(b[(k + 8) * P.sb]), b3 = to_acc(b[(k + 12) * P.sb]);
+        // four rows per wave per step; the next step's rows are loaded before
+        // this step's are added, so eight are in flight
+        auto load4 = [&](int64_t k0, TA (&x)[4][VEC], TA (&bk)[4]) {
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) {
-                acc[v] += x0[v] * b0;
-                acc[v] += x1[v] * b1;
-                acc[v] += x2[v] * b2;
-                acc[v] += x3[v] * b3;
+            for (int r = 0; r < 4; ++r) {
+                if constexpr (VEC > 1) load_vec<TI, VEC>(Ap + (k0 + 4 * r) * P.sA_k, x[r]);
+                else x[r][0] = to_acc(Ap[(k0 + 4 * r) * P.sA_k]);
+                bk[r] = to_acc(b[(k0 + 4 * r) * P.sb]);
             }
+        };
+        if (k + 12 < ke) {
+            TA x[4][VEC], bx[4];
+            load4(k, x, bx);
+            for (; k + 28 < ke; k += 16) {
+                TA y[4][VEC], by[4];
+                load4(k + 16, y, by);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) acc[v] += x[r][v] * bx[r];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    bx[r] = by[r];
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) x[r][v] = y[r][v];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) acc[v] += x[r][v] * bx[r];
+            k += 16;
         }
         for (; k < ke; k += 4) {
             TA x0[VEC];

@@ -131,6 +131,20 @@ def test_autotune_ttm_ttt(T):
             assert "autotuned" in T.plan(T.ttm, Ad, Bd, q, out=again)
             assert np.array_equal(to_np(again), first)
         assert T.autotune_entries() == 2 * (len(cases) + 1)
+        # a new shape of an already tuned class (13^4 -> 14^4, mode 3, m = 64):
+        # frozen, it takes the class's choice; on, it is tuned for itself and
+        # adds its own entry only
+        X = synth.uniform((14, 14, 14, 14), g)
+        B = synth.uniform((64, 14), g)
+        Ad, Bd = to_gpu(X, [1, 2, 3, 4], "f64"), to_gpu(B, None, "f64")
+        C = T.empty((14, 14, 64, 14), None, torch.float64, "cuda")
+        assert "autotuned(class)" in T.plan(T.ttm, Ad, Bd, 3, out=C)
+        T.set_autotune("on")
+        T.ttm(Ad, Bd, 3, out=C)
+        torch.cuda.synchronize()
+        assert T.autotune_entries() == 2 * (len(cases) + 1) + 1
+        ref = oracle.ttm(oracle.materialize(X), B, 3)
+        assert_close(to_np(C), ref, TOL["f64"], "tuned within a known class")
     finally:
         T.set_autotune(prev)
         T.autotune_clear()
