@@ -185,6 +185,35 @@ def build_cases(T, torch, dev, quick=False):
     return cases, keep, outbuf
 
 
+def hbm_ceilings(nbytes=4 << 30, reps=10):
+    """Plain HBM streams timed with events on 4 GiB buffers: torch's fill_
+    (write only), copy_ (read + write) and sum (read only), FP32 and FP64, in
+    GB/s of bytes moved.  These are practical ceilings on this GPU for the
+    kernels' write-, copy- and read-dominated regimes (the published 8 TB/s
+    stays the roofline peak)."""
+    import torch
+
+    out = {"bytes": nbytes, "reps": reps}
+    for name, dt in (("f32", torch.float32), ("f64", torch.float64)):
+        n = nbytes // torch.tensor([], dtype=dt).element_size()
+        x = torch.ones(n, dtype=dt, device="cuda:0")
+        y = torch.empty_like(x)
+        for what, fn, moved in (("fill", lambda: y.fill_(2.0), nbytes), ("copy", lambda: y.copy_(x), 2 * nbytes),
+                                ("sum", lambda: x.sum(), nbytes)):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            out["%s_%s_GBps" % (what, name)] = round(moved * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+        del x, y
+        torch.cuda.empty_cache()
+    return out
+
+
 def recorded_traffic(label):
     """HBM bytes per launch for kernel `label` from a committed rocprofv3
     summary under profiles/ (FETCH_SIZE and WRITE_SIZE, each scaled by the same
@@ -908,7 +937,13 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (3 times), the reference for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale")
+    ap.add_argument("--ceilings", action="store_true",
+                    help="only time plain 4 GiB HBM streams (torch fill_, copy_ and sum in FP32 and FP64): "
+                         "practical write, copy and read rates to set the kernels' fractions against")
     args = ap.parse_args()
+    if args.ceilings:
+        print(json.dumps(hbm_ceilings()))
+        return
     if args.cpu_baseline_only:
         print(json.dumps(cpu_baseline(args.cpu_budget)))
         return

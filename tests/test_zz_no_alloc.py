@@ -42,6 +42,8 @@ def test_ttt_noalloc_matches_ttt_on_two_calls(dtype, bar):
     cases = [((96, 80, 64, 48), (64, 48, 120), (3, 1, 4, 2)),
              ((40, 24, 40, 36), (40, 36, 56), (1, 2, 3, 4))]
     side = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(side):
+        T.workspace_release()  # torch hands out pooled streams: start without a buffer
     for na, nb, lay in cases:
         A, B = _case(na, nb, lay, dtype, gen, dev)
         nc = (na[0], na[1], nb[2])
