@@ -890,12 +890,14 @@ static int plan_gemm(int dtype, int x_is, const void* X, const void* Y, void* C,
     // loads run along memory.
     ndk = coalesce(dk, ndk, 2, M > N ? 0 : 1);
 
-    // Packed X: a small X (at most 4M elements and a sixteenth of Y's bytes)
-    // whose first K dim does not have unit stride while Y's does is copied
-    // into the workspace as an M x K matrix with k fastest, in the K order
-    // chosen above, so that the GEMM loads groups of consecutive k from both
-    // operands (16-bit MFMA operands take eight, FP32/FP64 loads two).  The
-    // copy's dims are K's then M's, with X's strides and the packed ones.
+    // Packed X: a small X (at most 4M elements and a sixteenth of Y's
+    // elements, Y at least 4 MB) whose first K dim does not have unit stride
+    // is copied into the workspace as an M x K matrix with k fastest, in the
+    // K order chosen above (Y's), so that the GEMM loads groups of
+    // consecutive k of X (16-bit MFMA operands take eight, FP32/FP64 loads
+    // two), and K's dims merge wherever Y's do (one K dim lets Y load vectors
+    // along N).  The copy's dims are K's then M's, with X's strides and the
+    // packed ones.
     GDims xpack{};
     size_t xwsb = 0;
     Dim dm0[MAXP], dk0[MAXP];
@@ -904,8 +906,9 @@ static int plan_gemm(int dtype, int x_is, const void* X, const void* Y, void* C,
     for (int i = 0; i < ndk; ++i) dk0[i] = dk[i];
     {
         const int gv = (dtype == TLIB_BF16 || dtype == TLIB_F16) ? 8 : 2;
-        if (ws_cap == SIZE_MAX && ndk >= 1 && ndk + ndm <= MAXP && dk[0].s[0] != 1 && dk[0].s[1] == 1 &&
-            dk[0].n % gv == 0 && M * K <= (int64_t(1) << 22) && 16 * M <= N && K >= 64) {
+        if (ws_cap == SIZE_MAX && ndk >= 1 && ndk + ndm <= MAXP && dk[0].s[0] != 1 && dk[0].n % gv == 0 &&
+            M * K <= (int64_t(1) << 22) && 16 * M <= N && K >= 64 &&
+            N * K * int64_t(esize(dtype)) >= (int64_t(4) << 20)) {
             int64_t st = 1;
             for (int i = 0; i < ndk; ++i) {
                 xpack.n[xpack.nd] = dk[i].n;
@@ -924,6 +927,7 @@ static int plan_gemm(int dtype, int x_is, const void* X, const void* Y, void* C,
             xpack.total = st;
             xwsb = size_t(st) * size_t(esize(dtype));
             X = reinterpret_cast<const void*>(uintptr_t(WS_ALIGN));  // workspace pieces are 256-byte aligned
+            ndk = coalesce(dk, ndk, 2, 1);
         }
     }
 

@@ -60,9 +60,18 @@ template <> struct Mfma<f16_t> {
 
 // K slice depth of a tile: 16-bit slices hold four MFMA k-steps (two for
 // tiles with BM + BN > 256, whose 128-deep slices would leave room for only
-// one workgroup per CU).
-template <typename TI, int BM, int BN> struct SliceK {
-    static constexpr int value = sizeof(TI) == 2 && BM + BN > 256 ? 64 : Mfma<TI>::BK;
+// one workgroup per CU) when both operands load 16-byte vectors (YW bit 0,
+// and bit 1 or 2); an operand loaded element by element holds one register
+// per element in flight, so its slices keep one k-step (deeper ones spill),
+// or as many as one pass of Y's transposed vector stash covers.  The planner
+// rounds K ranges to the deepest slice, a multiple of all of them.
+template <typename TI, int BM, int BN, int YW = 7> struct SliceK {
+    static constexpr bool VEC16 = (YW & 1) != 0 && (YW & 6) != 0;
+    static constexpr int SHALLOW = (YW & 4) != 0 && 2048 / BN > 32 ? 2048 / BN : 32;
+    static constexpr int value = sizeof(TI) != 2 ? Mfma<TI>::BK
+                                 : !VEC16        ? SHALLOW
+                                 : BM + BN > 256 ? 64
+                                                 : Mfma<TI>::BK;
 };
 
 __device__ __forceinline__ d4_t mfma_step(double a, double b, d4_t c) {
@@ -105,7 +114,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
     using RT = typename Raw<TI>::type;
     using acc_t = typename Mfma<TI>::acc_t;
     constexpr bool WIDE = sizeof(TI) == 2;
-    constexpr int BK = SliceK<TI, BM, BN>::value;
+    constexpr int BK = SliceK<TI, BM, BN, YW>::value;
     constexpr int KSTEP = Mfma<TI>::KSTEP;
     constexpr int WM = BM / WGM, WN = BN / WGN;
     constexpr int FM = WM / 16, FN = WN / 16;

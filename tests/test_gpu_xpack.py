@@ -1,9 +1,10 @@
 """GPU parity of TTT with the small operand packed first (Sec. 5.2 Eq. ttt,
 ttt_indices).  When the large operand's contracted modes run along memory in
-an order in which the small operand's do not (A last-order, B first-order),
-the planner copies the small operand into the workspace as a matrix with its
-contracted index fastest, in the large operand's order, and the GEMM then
-loads groups of consecutive k from both.  Every tiled pick (seven tiles, three
+an order in which the small operand's do not (A last-order, B first-order;
+or A first-order, B last-order), the planner copies the small operand into the
+workspace as a matrix with its contracted index fastest, in the large
+operand's order, and the GEMM then loads groups of consecutive k of it (and
+K's modes merge wherever the large operand's do).  Every tiled pick (seven tiles, three
 split targets) and every all-rows pick is forced through a one-entry kernel
 table and compared with the oracle on the same rounded inputs (FP64 1e-12,
 FP32 1e-5, 16-bit 1e-5); the plan must name the packing.  Cases: ragged free
@@ -45,29 +46,33 @@ def _force(T, tmp_path, A, B, C, q, phi, psi, pick):
     T.autotune_load(str(f))
 
 
-# (A extents, number of contracted modes q (A's last q), B's free extents, B a view padded along its last mode)
-CASES = [((20, 24, 16, 8), 2, (5,), 0),       # M = 5, K = 128: (16, 8) with A's stride-1 mode last
-         ((31, 17, 24, 8), 2, (7,), 0),       # ragged N = 527, M = 7
-         ((60, 8, 6, 8), 3, (3,), 0),         # three contracted modes, K = 384
-         ((30, 20, 16, 8), 2, (2, 3), 5)]     # B a strided view, two free B modes
+# (A extents, number of contracted modes q (A's last q), B's free extents, B a
+# view padded along its last mode, A layout, B layout); A is at least 4 MB in
+# every dtype, as packing requires
+CASES = [((64, 64, 32, 16), 2, (5,), 0, "last", "first"),       # M = 5, K = 512
+         ((67, 31, 48, 24), 2, (7,), 0, "last", "first"),       # ragged N = 2077, M = 7
+         ((1024, 8, 24, 16), 3, (3,), 0, "last", "first"),      # three contracted modes, K = 3072
+         ((64, 64, 32, 16), 2, (2, 3), 5, "last", "first"),     # B a strided view, two free B modes
+         ((96, 64, 32, 16), 2, (6,), 0, "first", "last")]       # K merges after packing: A loads vectors along N
 
 
 @pytest.mark.parametrize("dtype", ["bf16", "f16", "f32", "f64"])
 def test_ttt_packed_small_operand(T, tmp_path, dtype):
     import torch
     g = synth.rng(76, ["bf16", "f16", "f32", "f64"].index(dtype))
-    for na, q, fb, pad in CASES:
+    for na, q, fb, pad, la, lb in CASES:
         p = len(na)
         ka = na[p - q:]
         nb = ka + fb
         X, Y = synth.uniform(na, g), synth.uniform(nb, g)
-        Ad = to_gpu(X, list(range(p, 0, -1)), dtype)   # last-order A
+        Ad = to_gpu(X, list(range(p, 0, -1)) if la == "last" else None, dtype)
+        blay = list(range(len(nb), 0, -1)) if lb == "last" else None
         if pad:
             big = np.zeros(nb[:-1] + (nb[-1] + pad,))
             big[..., : nb[-1]] = Y
-            Bd = to_gpu(big, None, dtype)[..., : nb[-1]]
+            Bd = to_gpu(big, blay, dtype)[..., : nb[-1]]
         else:
-            Bd = to_gpu(Y, None, dtype)                # first-order B
+            Bd = to_gpu(Y, blay, dtype)
         phi = tuple(range(1, p + 1))
         psi = tuple(range(q + 1, len(nb) + 1)) + tuple(range(1, q + 1))
         ref = np.asarray(oracle.ttt(oracle.materialize(round_to(X, dtype)), oracle.materialize(round_to(Y, dtype)),
