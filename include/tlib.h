@@ -206,8 +206,14 @@ int tlib_times_vectors(const tlib_tensor* A, const tlib_tensor* const* us, int32
  * not alias each other's outputs.  A request whose index groups do not
  * collapse to at most four (extent, stride) pairs each (and 2^31 indices) is
  * rejected with TLIB_ESTRIDE and its index in *bad (run it with the single
- * entry points instead; tlib_request_groupable tells in advance).  *units
- * receives the number of work units. */
+ * entry points instead; tlib_request_groupable tells in advance).  A request
+ * whose contraction (n_m for TTV / TTM, the product of the contracted extents
+ * for TTT) exceeds TLIB_BATCH_MAX_K is rejected the same way with
+ * TLIB_EINVAL: a grouped thread or tile accumulates the whole contraction in
+ * one chain, and the single entry points split long ones, which keeps FP32
+ * results within their error bound.  *units receives the number of work
+ * units. */
+#define TLIB_BATCH_MAX_K 8192
 typedef struct {
     int32_t op;              /* 0 = TTV, 1 = TTM, 2 = TTT */
     int32_t mode;            /* TTV / TTM: m, 1-based */

@@ -2319,6 +2319,12 @@ static int batch_request(const tlib_request& r, BatchItem& it) {
     if (rc) return rc;
     if (!batch_item(r.op, a, b, c, r.mode - 1, r.q, r.phi, r.psi, it))
         return fail(TLIB_ESTRIDE, "batch: a request does not collapse to the grouped kernel's index groups");
+    // one grouped thread or tile carries the whole contraction in one FP32
+    // (or FP64) accumulator chain; longer ones go to the single entry points,
+    // whose split-K keeps the chains short
+    if (it.K > TLIB_BATCH_MAX_K)
+        return fail(TLIB_EINVAL, "batch: contraction of %lld exceeds the grouped kernel's %d", (long long)it.K,
+                    TLIB_BATCH_MAX_K);
     return TLIB_OK;
 }
 

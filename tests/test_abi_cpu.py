@@ -558,3 +558,43 @@ def test_plan_cache_reuses_plans():
         assert _cache_stats()[0] == e0 + 2
     L.tlib_plan_cache_clear()
     assert _cache_stats()[0] == 0
+
+
+def test_grouped_launch_rejects_long_contractions():
+    """A grouped thread or tile carries a request's whole contraction in one
+    accumulator chain, so requests with a contraction above TLIB_BATCH_MAX_K
+    (8192) are not groupable; the single entry points split them.  TTV with
+    n_m = 8192 / 8193 and TTT contracting every mode of A (K = 8192 / 9000)."""
+    L = _lib.lib()
+
+    def req(op, A, B, C, mode=0, q=0, phi=None, psi=None):
+        r = _lib.Request()
+        r.op, r.mode, r.q = op, mode, q
+        r.A, r.B, r.C = ctypes.pointer(A), ctypes.pointer(B), ctypes.pointer(C)
+        keep = []
+        if phi is not None:
+            pa, pb = _lib.i32_array(phi), _lib.i32_array(psi)
+            keep += [pa, pb]
+            r.phi = ctypes.cast(pa, ctypes.POINTER(ctypes.c_int32))
+            r.psi = ctypes.cast(pb, ctypes.POINTER(ctypes.c_int32))
+        return r, keep
+
+    for nk, want in ((8192, 1), (8193, 0)):
+        A = _d((nk, 3), _lib.F32)
+        b = _d((nk,), _lib.F32, ptr=FAKE * 2)
+        C = _d((3,), _lib.F32, ptr=FAKE * 3)
+        r, keep = req(0, A, b, C, mode=1)
+        assert L.tlib_request_groupable(ctypes.byref(r)) == want, nk
+    for shape, want in (((64, 128), 1), ((90, 100), 0)):
+        A = _d(shape, _lib.F32)
+        B = _d(shape + (8,), _lib.F32, ptr=FAKE * 2)
+        C = _d((8,), _lib.F32, ptr=FAKE * 3)
+        r, keep = req(2, A, B, C, q=2, phi=(1, 2), psi=(3, 1, 2))
+        assert L.tlib_request_groupable(ctypes.byref(r)) == want, shape
+    # the batch planner rejects the long one with TLIB_EINVAL and names it
+    arr = (_lib.Request * 1)(r)
+    nbytes = L.tlib_batch_table_bytes(1)
+    host = (ctypes.c_char * nbytes)()
+    units, bad = ctypes.c_int64(0), ctypes.c_int32(-1)
+    assert L.tlib_batch_plan(arr, 1, host, nbytes, ctypes.byref(units), ctypes.byref(bad)) == _lib.EINVAL
+    assert bad.value == 0 and b"8192" in L.tlib_last_error()
