@@ -763,15 +763,19 @@ def views_bench(args):
         g = torch.Generator(device=dev)
         g.manual_seed(171110912 + 5)
         views = {
-            "dense": T.empty((n, n, n, n), None, dt, dev),
-            "sliced": T.empty((2 * n, n + 3, n, n), None, dt, dev)[:n, :n],
-            "step2_mode1": T.empty((2 * n, n, n, n), None, dt, dev)[::2],
-            "trim": T.empty((n + 2, n + 2, n + 2, n + 2), None, dt, dev)[1:n + 1, 1:n + 1, 1:n + 1, 1:n + 1],
-            "step3_mode2_last": T.empty((n, 3 * n, n, n), [4, 3, 2, 1], dt, dev)[:, ::3],
-            "step2_mode4_perm": T.empty((n, n, n, 2 * n), [2, 4, 1, 3], dt, dev)[:, :, :, ::2],
+            "dense": lambda: T.empty((n, n, n, n), None, dt, dev),
+            "sliced": lambda: T.empty((2 * n, n + 3, n, n), None, dt, dev)[:n, :n],
+            "step2_mode1": lambda: T.empty((2 * n, n, n, n), None, dt, dev)[::2],
+            "trim": lambda: T.empty((n + 2, n + 2, n + 2, n + 2), None, dt, dev)[1:n + 1, 1:n + 1, 1:n + 1, 1:n + 1],
+            "step3_mode2_last": lambda: T.empty((n, 3 * n, n, n), [4, 3, 2, 1], dt, dev)[:, ::3],
+            "step2_mode4_perm": lambda: T.empty((n, n, n, 2 * n), [2, 4, 1, 3], dt, dev)[:, :, :, ::2],
         }
-        for name, A in views.items():
+        for name, make in views.items():
+            # inner and add read a second tensor of the same view kind, so
+            # that every counted byte is read from its own address
+            A, A2 = make(), make()
             A.copy_(torch.rand(A.shape, generator=g, device=dev, dtype=dt))
+            A2.copy_(torch.rand(A2.shape, generator=g, device=dev, dtype=dt))
             N = A.numel()
             ops = []
             for q in range(1, 5):
@@ -787,9 +791,9 @@ def views_bench(args):
                             T.plan(T.ttm, A, B, q, out=C).split(" ")[1]))
             r = torch.empty((), dtype=torch.float64, device=dev)
             ops.append(("norm", s * N, (lambda A=A, r=r: T.norm(A, out=r)), "dot"))
-            ops.append(("inner", 2 * s * N, (lambda A=A, r=r: T.inner(A, A, out=r)), "dot"))
+            ops.append(("inner", 2 * s * N, (lambda A=A, A2=A2, r=r: T.inner(A, A2, out=r)), "dot"))
             Cd = T.empty(A.shape, None, dt, dev)
-            ops.append(("add", 3 * s * N, (lambda A=A, Cd=Cd: T.add(1.0, A, 1.0, A, out=Cd)), "ewise"))
+            ops.append(("add", 3 * s * N, (lambda A=A, A2=A2, Cd=Cd: T.add(1.0, A, 1.0, A2, out=Cd)), "ewise"))
             rec = {}
             tb = tt = 0.0
             for label, nbytes, fn, kern in ops:
