@@ -955,13 +955,18 @@ static int plan_gemm(int dtype, int x_is, const void* X, const void* Y, void* C,
         {
             // Y as vectors along N: FP32/FP64, N's first dim of unit stride in
             // Y, K one dim; 16-byte vectors when K's stride keeps them
-            // aligned, else 8-byte ones (FP32) when it keeps those aligned
-            // (16-bit: eight elements, stored transposed into the slice)
+            // aligned, else 8-byte ones (FP32) when it keeps those aligned.
+            // 16-bit: eight elements, stored transposed into the slice with
+            // one 2-byte LDS write each and 128-deep slices, which pays only
+            // on long contractions (TTT, K = 3072: 42 against 43 us) and
+            // costs on short ones (the BF16 Tucker chain's TTMs, K = 160:
+            // 1.67 against 0.94 ms), so it needs K >= 1024.
             P.syk = ndk == 1 ? dk[0].s[1] : 0;
             P.y_vec = 0;
             if (!P.y_kfast && ndk == 1 && ndn >= 1 && dn[0].s[0] == 1) {
                 const int v16 = 16 / esize(dtype);
-                if (P.syk % v16 == 0 && (uintptr_t(Y) % 16) == 0) P.y_vec = v16;
+                if (P.syk % v16 == 0 && (uintptr_t(Y) % 16) == 0 && (esize(dtype) > 2 || K >= 1024))
+                    P.y_vec = v16;
                 else if (dtype == TLIB_F32 && P.syk % 2 == 0 && (uintptr_t(Y) % 8) == 0) P.y_vec = 2;
             }
         }

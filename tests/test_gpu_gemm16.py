@@ -145,9 +145,10 @@ TILES = ["16x256", "64x128", "128x128", "256x64", "64x64", "128x64", "256x32"]
 # (free A extents, contracted extents, free B extents, vectors expected)
 # A's first mode may be a view of a longer one (pad): columns then run in
 # pieces of that extent, spaced by the padded length.
-VEC_CASES = [((40,), (24, 40), (3,), 0, True),          # N = 40 ragged against every tile
+VEC_CASES = [((40,), (24, 48), (3,), 0, True),          # N = 40 ragged against every tile
              ((12, 6), (64, 48), (5,), 16, True),       # runs of 12 columns 16 apart: some waves load singly
-             ((37,), (24, 40), (2, 3), 0, False)]       # K stride 37: no 16-byte alignment
+             ((37,), (24, 48), (2, 3), 0, False),       # K stride 37: no 16-byte alignment
+             ((40,), (16, 40), (3,), 0, False)]         # K = 640 < 1024: element by element, one k-step slices
 
 
 @pytest.mark.parametrize("dtype", ["bf16", "f16"])
@@ -158,7 +159,8 @@ def test_ttt_16bit_vectors_along_n(T, tmp_path, dtype, tile):
     transposed into the LDS slice, for every tile shape (forced through a
     one-entry kernel table), with ragged N, column runs that end inside a
     wave (such waves load column by column), a K stride that rules vectors
-    out, and K long enough for several slices and a split (Sec. 5.2 Eq. ttt)."""
+    out, a K too short for them (below 1024), and K long enough for several
+    slices and a split (Sec. 5.2 Eq. ttt)."""
     import torch
     g = synth.rng(72, tile + (0 if dtype == "bf16" else 7))
     for fa, ka, fb, pad, vec in VEC_CASES:
