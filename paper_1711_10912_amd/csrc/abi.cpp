@@ -1583,7 +1583,8 @@ int tlib_ttm(const tlib_tensor* A, const tlib_tensor* B, int32_t m, const tlib_t
     }
     static const int cands[] = {TTM_PICK_STREAM,          TTM_PICK_ROWS_PLAIN,        TTM_PICK_GEMM + GT_COUNT,
                                 TTM_PICK_GEMM + GT_128x64, TTM_PICK_GEMM + GT_128x128, TTM_PICK_GEMM + GT_64x128,
-                                TTM_PICK_GEMM + GT_256x64, TTM_PICK_GEMM + GT_COUNT + 1, TTM_PICK_GEMM + GT_COUNT + 2};
+                                TTM_PICK_GEMM + GT_256x64, TTM_PICK_GEMM + GT_64x64,   TTM_PICK_GEMM + GT_COUNT + 1,
+                                TTM_PICK_GEMM + GT_COUNT + 2};
     std::string key = "ttm";
     key_int(key, m);
     key_ten(key, a);
