@@ -169,17 +169,21 @@ def build_cases(T, torch, dev, quick=False):
     for d in ("f32", "bf16", "f16"):
         for lname, lay in (("first", (1, 2, 3, 4)), ("last", (4, 3, 2, 1)), ("perm3142", (3, 1, 4, 2))):
             sets = []
-            for c in range(6 if not quick else 2):
+            nsets = 6 if not quick else 2
+            for c in range(nsets):
+                # the last set is the x1e3 variant that exercises range
+                sc = 1e3 if c == nsets - 1 else 1.0
                 A = T.empty(na, lay, tdt[d], dev)
-                A.copy_(torch.randn(na, generator=gen, device=dev, dtype=torch.float32).to(tdt[d]))
-                B = torch.randn(nbs, generator=gen, device=dev, dtype=torch.float32).to(tdt[d])
+                A.copy_(torch.randn(na, generator=gen, device=dev, dtype=torch.float32).mul_(sc).to(tdt[d]))
+                B = torch.randn(nbs, generator=gen, device=dev, dtype=torch.float32).mul_(sc).to(tdt[d])
                 B = T.empty(nbs, None, tdt[d], dev).copy_(B)
                 C = T.empty((96, 80, 120), None, torch.float32, dev)
                 sets.append((A, B, C))
             keep.extend(sets)
             nbytes = ESZ[d] * (96 * 80 * 64 * 48 + 64 * 48 * 120) + 4 * Mt * Nt
             for c, (A, B, C) in enumerate(sets):
-                cases.append(Case("ttt A=%s %s set=%d" % (lname, d, c), "ttt", nbytes, 2 * Mt * Nt * Kt, d,
+                tag = "x1e3" if c == len(sets) - 1 else "set=%d" % c
+                cases.append(Case("ttt A=%s %s %s" % (lname, d, tag), "ttt", nbytes, 2 * Mt * Nt * Kt, d,
                                   (lambda A=A, B=B, C=C: T.ttt(A, B, 2, phi, psi, out=C))))
                 cases[-1].planfn = _plan_later(T, T.ttt, A, B, 2, phi, psi, out=C)
     return cases, keep, outbuf
@@ -1118,7 +1122,8 @@ def main():
         "data": "synthetic (seeded uniform[-1,1] / normal(0,1) on device)",
         "config": {"workload": "order-p sweep p=3..7 (406^3,90^4,36^5,20^6,13^7), every mode, first+last order, "
                                "f64+f32: TTV, TTM m=16/64/256, inner, norm, add; plus TTT (96,80,64,48)x(64,48,120) "
-                               "A{3,4}<->B{1,2}, 3 A layouts, f32/bf16/f16; outer product (512,128)x(64,40) f64+f32"
+                               "A{3,4}<->B{1,2}, 3 A layouts, f32/bf16/f16, one input set of six at x1e3; "
+                               "outer product (512,128)x(64,40) f64+f32"
                                + (" [quick: p=3,7 only]" if args.quick else "")
                                + (" [families: %s]" % args.families if args.families else ""),
                    "served": None if args.no_serve else "mixed stream of %d requests (see the served object)"
