@@ -28,6 +28,18 @@ typedef float f4s_t __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ f4s_t swz4(f4s_t a, int g) {
     return g == 0 ? a : g == 1 ? a.yxwz : g == 2 ? a.zwxy : a.wzyx;
 }
+
+// Buffer resource of a wave-uniform range.  The address and size are taken
+// from the first lane so that the descriptor lives in scalar registers: the
+// compiler cannot always prove them uniform and would otherwise wrap every
+// store in a loop over the distinct descriptors of the wave.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t wave_rsrc(const void* p, uint32_t nbytes) {
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(a));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(a >> 32));
+    return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>((uint64_t(hi) << 32) | lo), 0,
+                                             int(__builtin_amdgcn_readfirstlane(nbytes)), 0x00020000);
+}
 typedef __bf16 bf8s_t __attribute__((ext_vector_type(8)));
 typedef _Float16 h8s_t __attribute__((ext_vector_type(8)));
 typedef uint32_t u4s_t __attribute__((ext_vector_type(4)));
@@ -379,7 +391,7 @@ __global__ __launch_bounds__(256) void ttm_rows_kernel(TtmRowParams P) {
             live & (BAND ? uint32_t(nrows * P.n_lo) * uint32_t(sizeof(TA))
                          : uint32_t((int64_t(nrows - 1) * P.sCm + int64_t(P.n_lo - 1) * P.sClo + 1) *
                                     int64_t(sizeof(TA))));
-        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(base, 0, int(nbytes), 0x00020000);
+        const __amdgpu_buffer_rsrc_t rs = wave_rsrc(base, nbytes);
         // Stage layout: FP64 row-major, the four rows kq of result register
         // pc; FP32 column-major with the four rows 4kq..4kq+3 of a result
         // register written as one 16-byte vector (permuted as stage_at reads
@@ -428,6 +440,79 @@ __global__ __launch_bounds__(256) void ttm_rows_kernel(TtmRowParams P) {
             }
         }
     };
+    // FP32 results of the aligned and band modes: a whole 16-row block is
+    // staged once and written with 16-byte stores (each lane four
+    // consecutive elements of a row window or of the block's linear range),
+    // a quarter of the store instructions of the piece-wise path.  It takes
+    // blocks of 16 rows whose windows lie inside the run (aligned: not the
+    // first or last chunk; each window starts on a 128-byte line by design)
+    // or whose linear range starts 16-byte aligned (band); other blocks go
+    // the piece-wise way.
+    constexpr bool VBLK = !F64 && MODE != TTM_ROWS_PLAIN;
+    auto store_block_vec = [&](int i, const acc_t (&acc)[FN], int64_t yc, int t, int c0) -> bool {
+      if constexpr (!VBLK) {
+        return false;
+      } else {
+        const int j0 = row0 + i * 16;
+        const int nrows = max(0, min(16, P.M - j0));
+        TA* base = C + yc + int64_t(j0) * P.sCm;
+        // whole blocks only: 16 rows, and (band) a 16-byte aligned range or
+        // (aligned windows) every row's window inside the run
+        if (nrows < 16) return false;
+        if (BAND && (reinterpret_cast<uintptr_t>(base) & 15) != 0) return false;
+        if (!BAND && (t == 0 || W * t + W > P.n_lo)) return false;
+        const uint32_t live = nrows > 0 ? 0xffffffffu : 0u;
+        const uint32_t nbytes =
+            live & (BAND ? uint32_t(nrows * P.n_lo) * uint32_t(sizeof(TA))
+                         : uint32_t((int64_t(nrows - 1) * P.sCm + int64_t(P.n_lo - 1) * P.sClo + 1) *
+                                    int64_t(sizeof(TA))));
+        const __amdgpu_buffer_rsrc_t rs = wave_rsrc(base, nbytes);
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            *reinterpret_cast<f4s_t*>(&stg[(j * 16 + rl) * SPC + 4 * kq]) = swz4(acc[j], SWZ ? j & 3 : 0);
+        // four elements at byte offset off, all inside or all outside the
+        // range (lanes past its end get an out-of-range offset)
+        auto put4 = [&](const f4s_t& v, bool ok, uint32_t off) {
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4s_t, v), rs, int(ok ? off : OOB), 0, 0);
+        };
+        if constexpr (BAND) {
+            constexpr int MAXLEN = 16 * (MODE == TTM_ROWS_BAND1 ? 16 : MODE == TTM_ROWS_BAND ? 32 : 176);
+            const int len = nrows * P.n_lo;
+#pragma unroll
+            for (int it = 0; it < (MAXLEN + 255) / 256; ++it) {
+                // len = 16 n_lo is a multiple of 4: a lane's four are all in or all out
+                const int e = it * 256 + 4 * lane;
+                const bool ok = e < len;
+                int r = int(fdiv(uint32_t(ok ? e : 0), P.fd_lo));
+                int c = (ok ? e : 0) - r * P.n_lo;
+                f4s_t v;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    v[u] = stage_at(r, c);
+                    if (++c == P.n_lo) {
+                        c = 0;
+                        ++r;
+                    }
+                }
+                put4(v, ok, uint32_t(e) * uint32_t(sizeof(TA)));
+            }
+        } else {
+            // 16 lanes per row window, four rows per pass
+            const int rq = lane >> 4, qq = lane & 15;
+#pragma unroll
+            for (int pc = 0; pc < 4; ++pc) {
+                const int jr = 4 * pc + rq;
+                const int ws = W * t - int((reinterpret_cast<uintptr_t>(base + int64_t(jr) * P.sCm) & 127) / sizeof(TA));
+                const int col = ws + 4 * qq;  // inside the run: checked above
+                f4s_t v;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[u] = stage_at(jr, col + u - c0);
+                put4(v, true, uint32_t((int64_t(jr) * P.sCm + col) * int64_t(sizeof(TA))));
+            }
+        }
+        return true;
+      }
+    };
     Walk wk = xcd_walk(P.units, 4, wave, wblk, wgrid);
     const int nb = M16 / 16;
     for (; wk.u < wk.end; wk.u += wk.step) {
@@ -439,8 +524,12 @@ __global__ __launch_bounds__(256) void ttm_rows_kernel(TtmRowParams P) {
         for (int i = 0; i < nb; ++i) {
 #pragma unroll
             for (int q = 0; q < KS; ++q) mfma_step(i, q, acc);
+            bool done = false;
+            if constexpr (VBLK) done = store_block_vec(i, acc, yc, t, c0);
+            if (!done) {
 #pragma unroll
-            for (int q = 0; q < NPC; ++q) store_piece(i, q, acc, yc, t, c0);
+                for (int q = 0; q < NPC; ++q) store_piece(i, q, acc, yc, t, c0);
+            }
         }
     }
 }
