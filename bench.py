@@ -32,6 +32,7 @@ import json
 import math
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -342,6 +343,14 @@ def served_measure(n_req, slots=4, budget=64 << 30, check=True, log=None, table=
         return srv.stats()
 
     srv = Server(hbm_budget=budget, slots=slots)
+    # the served stream runs on its own kernel table only; the caller's
+    # entries (the sweep's) come back for the plain per-call baseline below
+    kept = None
+    if T.autotune_entries():
+        fd, kept = tempfile.mkstemp(suffix=".txt")
+        os.close(fd)
+        T.autotune_save(kept)
+    T.autotune_clear()
     tuning = {"table": None, "mode": "off"}
     if tune_save:
         # one untimed pass with autotuning on: every new shape class is tuned
@@ -379,6 +388,10 @@ def served_measure(n_req, slots=4, budget=64 << 30, check=True, log=None, table=
     del tie
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
+    T.autotune_clear()
+    if kept:
+        T.autotune_load(kept)
+        os.remove(kept)
 
     # plain per-call FP64: the same requests, one synchronous call each
     cache = {}
