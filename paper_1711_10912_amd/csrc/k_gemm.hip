@@ -457,7 +457,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
     }
     // Staged epilogue: each wave writes one 16-row block of its tile to LDS,
     // then stores whole rows with lanes running along C's columns (16-byte
-    // vector stores when C's column strides allow it).
+    // vector stores when C's column strides allow it).  The staging rows are
+    // the wave's own (the K loop's last barrier has already separated them
+    // from the other waves' operand reads), so the waves go through their
+    // blocks without waiting for each other.
     TA* C = (TA*)P.C;
     TA* stg = reinterpret_cast<TA*>(smem) + wave * 16 * SP;
     constexpr int V = 16 / int(sizeof(TA));
@@ -474,7 +477,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
         for (int j = 0; j < FN; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) stg[(RQ * kq + RR * r) * SP + j * 16 + rl] = acc[i][j][r];
-        __syncthreads();
 #pragma unroll
         for (int rr = lane / LPR; rr < 16; rr += RPI) {
             const int64_t ro = crow[wm0 + i * 16 + rr];
@@ -490,7 +492,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
                 }
             }
         }
-        __syncthreads();
     }
 }
 
