@@ -1960,7 +1960,7 @@ static int run_dot(const Ten& a, const Ten* b, double* out, bool sq, hipStream_t
     int nd = coalesce(d, a.p, 2, 0);
     GDims g;
     fill_gdims(g, d, nd, 2);
-    int np = dot_partials(g.total);
+    int np = dot_partials_g(g);
     size_t wsb = size_t(np) * sizeof(double);
     plan_note("%s dot dtype=%s dims=%d total=%lld partials=%d", op, dname(a.dtype), nd,
               (long long)g.total, np);

@@ -305,6 +305,7 @@ int launch_gemm_generic(int dtype, const void* X, const void* Y, void* C, const 
 int launch_dot(int dtype, const void* A, const void* B, const GDims& d, double* out, bool sqrt_out,
                void* ws, size_t ws_bytes, hipStream_t s);
 int dot_partials(int64_t total);  // number of first-pass partials for a given size
+int dot_partials_g(const GDims& g);  // first-pass partials of a coalesced iteration space
 
 // C = A / den[0] (den in device memory) over GDims (strides s[0] = A, s[2] = C).
 int launch_div(int in_dtype, int out_dtype, const double* den, const void* A, void* C, const GDims& g,
