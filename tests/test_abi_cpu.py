@@ -352,6 +352,34 @@ def test_normalize_plan_and_errors():
         assert L.tlib_normalize(ctypes.byref(A), nrm, ctypes.byref(A2), None) == _lib.EALIAS
 
 
+def test_dot_partials_for_views():
+    """Inner/norm partition (Sec. 5.2 Table 3 inner product and norm): a dense
+    operand is one merged run split into a partial per 65536 elements (at most
+    2048); a view whose dims do not merge goes by rows and takes at least one
+    partial per 256 rows, up to 2048.  The workspace and the launch size their
+    partials by the same rule."""
+    L = _lib.lib()
+
+    def partials(shape, strides, dtype=_lib.F32):
+        A = _d(shape, dtype, strides=strides)
+        out = ctypes.c_void_p(FAKE * 3)
+        assert L.tlib_norm(ctypes.byref(A), out, None) == 0
+        p = _plan()
+        m = re.search(r"dims=(\d+) total=(\d+) partials=(\d+)", p)
+        assert m, p
+        return int(m.group(1)), int(m.group(2)), int(m.group(3))
+
+    with Plan():
+        # dense 90^4: one run, 65.6M elements -> ceil(65610000 / 65536) = 1002 partials
+        assert partials((90, 90, 90, 90), None) == (1, 90 ** 4, 1002)
+        # 90^4 window of a 100^4 parent: 729000 rows of 90 -> 2048 partials
+        assert partials((90, 90, 90, 90), (1, 100, 100 ** 2, 100 ** 3)) == (4, 90 ** 4, 2048)
+        # 1200 rows of 64: five partials (one per 256 rows), more than the two of the flat rule
+        assert partials((64, 30, 40), (1, 70, 70 * 31)) == (3, 64 * 30 * 40, 5)
+        # 100 rows of 10: one partial
+        assert partials((10, 10, 10), (1, 12, 144)) == (3, 1000, 1)
+
+
 def _tv(A, us, r, c):
     arr = (ctypes.POINTER(_lib.TensorDesc) * len(us))(
         *[ctypes.pointer(u) if u is not None else ctypes.POINTER(_lib.TensorDesc)() for u in us])
