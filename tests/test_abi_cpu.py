@@ -352,6 +352,30 @@ def test_normalize_plan_and_errors():
         assert L.tlib_normalize(ctypes.byref(A), nrm, ctypes.byref(A2), None) == _lib.EALIAS
 
 
+def test_ttv_col_vector_width():
+    """TTV col regime (Sec. 5.2 Eq. ttv): lanes along lo load the widest
+    vector the strides allow, narrowed only while it would leave fewer than
+    1024 workgroups; a k split then fills the chip."""
+    L = _lib.lib()
+
+    def plan(shape, q, dtype):
+        A = _d(shape, dtype)
+        b = _d((shape[q - 1],), dtype, ptr=FAKE * 2)
+        C = _d(tuple(n for i, n in enumerate(shape) if i != q - 1), dtype, ptr=FAKE * 3)
+        assert _ttv(A, b, q, C) == 0
+        p = _plan()
+        m = re.search(r"vec=(\d+) ksplit=(\d+) kr=\d+ blocks=(\d+)", p)
+        assert "ttv col" in p and m, p
+        return int(m.group(1)), int(m.group(2)), int(m.group(3))
+
+    with Plan():
+        # 406^3, mode 2: 16-byte vectors leave 4 x 406 = 1624 workgroups (>= 1024), split k in two
+        assert plan((406, 406, 406), 2, _lib.F64) == (2, 2, 3248)
+        assert plan((406, 406, 406), 2, _lib.F32)[0] == 2  # 4-wide: 812 < 1024, so 2-wide
+        # 200 x 200 x 20: vectors would leave 40 workgroups, scalar loads leave 80; k split six ways
+        assert plan((200, 200, 20), 2, _lib.F64) == (1, 6, 480)
+
+
 def test_dot_partials_for_views():
     """Inner/norm partition (Sec. 5.2 Table 3 inner product and norm): a dense
     operand is one merged run split into a partial per 65536 elements (at most
